@@ -1,0 +1,144 @@
+/*
+ * libsline -- s-line graphs of hypergraphs on AMD Instinct MI355X (gfx950).
+ *
+ * The s-line graph L_s(H) (paper, Sec. III): the items of H are its
+ * hyperedges e_1..e_m (or, for the dual hypergraph H*, its vertices); two
+ * distinct items a, b are adjacent in L_s(H) when their overlap
+ * w_ab = |S_a intersect S_b| is at least s, for an integer s >= 1.  L_1(H)
+ * is the ordinary line graph.  The paper's method (Sec. IV-B, IV-C) reaches
+ * this exact result by walking only pairs that share a member.
+ *
+ * Every call below is a plain C function taking plain pointers and sizes.
+ * Device pointers are HIP device addresses on the context's device; host
+ * pointers are ordinary process memory.  All calls are synchronous with
+ * respect to the host: when one returns, its device work has finished on the
+ * context's stream.  One context must not be used by two host threads at
+ * once.  Every function returns an sline_status; 0 is success.  A failed call
+ * leaves its output arguments untouched unless stated otherwise, and
+ * sline_last_error() then returns a message.
+ */
+#ifndef SLINE_H
+#define SLINE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sline_status;
+enum {
+    SLINE_OK = 0,
+    SLINE_EINVAL = -1,    /* malformed input: see sline_build                */
+    SLINE_ENOMEM = -2,    /* an allocation failed                            */
+    SLINE_ECAPACITY = -3, /* caller buffers too small; n_pairs holds the need */
+    SLINE_EDEVICE = -4,   /* a HIP runtime error; message in sline_last_error */
+    SLINE_EBUSY = -5      /* result not ready yet (server polling)           */
+};
+
+/* Build flags. */
+enum {
+    SLINE_SKIP_VALIDATE = 1u /* trust the CSR: skip the well-formedness check */
+};
+
+typedef struct sline_ctx sline_ctx;
+
+/* Device memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes usable on `stream` (NULL on failure); free releases it.  When no
+ * allocator is given the library uses hipMallocAsync / hipFreeAsync on the
+ * context's stream. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+    void *user;
+} sline_allocator;
+
+/* Incidence CSR of H with rows = hyperedges (the transpose of the paper's
+ * n x m incidence matrix I of Sec. III, eq. 1).  Device pointers, caller
+ * owned, read only, valid until the call returns.
+ *   row_ptr[n_edges + 1]: row_ptr[0] = 0, non-decreasing, row_ptr[n_edges] = nnz
+ *   col_idx[nnz]: members of hyperedge i are col_idx[row_ptr[i] .. row_ptr[i+1]),
+ *                 strictly increasing (a hyperedge is a set), each in
+ *                 [0, n_vertices).
+ * Empty rows, singleton rows, duplicate rows and isolated vertices are valid
+ * (the indexed-family definition of Sec. III). */
+typedef struct {
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    int32_t n_edges;
+    int32_t n_vertices;
+} sline_csr;
+
+/* An s-line graph as a structure of arrays, sorted by (a, b) ascending, with
+ * a < b and w = |S_a intersect S_b| >= s.  Device pointers.
+ *   capacity == 0 on input: the library allocates exactly n_pairs entries of
+ *                 a, b, w through the context's allocator; release them with
+ *                 sline_edges_free.
+ *   capacity > 0 on input: a, b, w are caller buffers of `capacity` entries.
+ *                 If the result needs more, the call returns SLINE_ECAPACITY
+ *                 with n_pairs = the entries needed, writes nothing else, and
+ *                 keeps its counting work: an immediate repeat of the same
+ *                 call with larger buffers only writes the result. */
+typedef struct {
+    int64_t n_pairs;
+    int64_t capacity;
+    int32_t *a;
+    int32_t *b;
+    int32_t *w;
+} sline_edges;
+
+/* Work figures of the last build on a context (host struct, filled by
+ * sline_last_stats). */
+typedef struct {
+    int64_t n_items;      /* items of the side built (m, or n for the dual)      */
+    int64_t nnz;          /* incidences of H                                      */
+    int64_t nnz_kept;     /* incidences of items with |S| >= s                    */
+    int64_t n_kept;       /* items with |S| >= s                                  */
+    int64_t wedges;       /* W_s: (a, v, b) with a < b, both kept, v shared       */
+    int64_t n_pairs;      /* |L_s|                                                */
+    int64_t n_small;      /* items counted by the one-wave kernel                 */
+    int64_t n_heavy;      /* items counted by the workgroup (multi-pass) kernel   */
+    int64_t passes;       /* table passes made by the workgroup kernel            */
+} sline_stats;
+
+/* Create a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  `alloc` may be NULL; it is
+ * copied.  Returns SLINE_EDEVICE if the device cannot be used. */
+sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream,
+                          const sline_allocator *alloc);
+
+/* Release a context and its workspace.  NULL is allowed. */
+void sline_destroy(sline_ctx *ctx);
+
+/* Build L_s(H) (dual = 0: items are hyperedges) or L_s(H*) (dual = 1: items
+ * are vertices, S_v = { i : v in e_i }) -- Sec. III; computed by counting,
+ * for each kept item a, the shared members of every item b > a reachable
+ * through a shared member (Sec. IV-B/IV-C: degree pruning of items with
+ * |S| < s, strictly upper triangle, each candidate counted once).
+ * Errors: SLINE_EINVAL for s < 1, negative sizes, NULL pointers with
+ * non-zero sizes, or (unless SLINE_SKIP_VALIDATE) a CSR that breaks the rules
+ * of sline_csr; SLINE_ENOMEM, SLINE_ECAPACITY, SLINE_EDEVICE as above.
+ * s larger than every item gives an empty result, not an error. */
+sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
+                         uint32_t flags, sline_edges *out);
+
+/* Release the arrays of a library-allocated result and zero the struct.
+ * Caller-owned buffers (capacity > 0) are not touched. */
+sline_status sline_edges_free(sline_ctx *ctx, sline_edges *edges);
+
+/* Statistics of the last successful build on `ctx`. */
+sline_status sline_last_stats(sline_ctx *ctx, sline_stats *stats);
+
+/* Static text for a status code. */
+const char *sline_status_str(sline_status status);
+
+/* Message of the last failed call on `ctx` ("" if none); valid until the next
+ * call on the context.  Includes the HIP error text for SLINE_EDEVICE. */
+const char *sline_last_error(sline_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLINE_H */

@@ -1,0 +1,573 @@
+// Host side of libsline: the C-ABI entry points of include/sline.h, the
+// context (stream, allocator, workspace) and the order of the device stages.
+//
+// sline_build, stage by stage (every stage is a HIP kernel of this library):
+//   1. row_ptr check, nnz read-back                      (one host sync)
+//   2. row ids, member range / order checks
+//   3. transpose: degree histogram, scan, atomic scatter, per-row sort
+//                                                        (one host sync for long rows)
+//   4. items / member lists chosen by the dual flag (H* swaps the roles, Sec. III)
+//   5. s-filtered member lists N_s(v) (degree-based pruning, Sec. IV-C)
+//   6. exact per-item wedge counts W_a, buckets (small / heavy by log2 W_a)
+//   7. count pass, exclusive scan of pairs per item      (one host sync)
+//   8. output allocation, fill pass                      (one host sync)
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "../../include/sline.h"
+#include "sline_internal.h"
+
+using namespace sl;
+
+struct sline_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sline_allocator alloc{};
+    bool has_alloc = false;
+    int n_cu = 256;
+    std::string last_error;
+    sline_stats stats{};
+    Tuning tune;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t *host = nullptr;  // pinned read-back area (64 int64)
+
+    // counting work kept after SLINE_ECAPACITY for an immediate retry
+    struct Pending {
+        bool valid = false;
+        sline_csr H{};
+        int32_t s = 0, dual = 0;
+        uint32_t flags = 0;
+        int64_t total = 0;
+    } pending;
+    // device views into the workspace kept for the fill pass
+    CountArgs fill_args{};
+    int64_t fill_total = 0;
+};
+
+namespace {
+
+struct Fail {
+    sline_status st;
+};
+
+void set_err(sline_ctx *c, const char *fmt, const char *detail = nullptr) {
+    char buf[512];
+    snprintf(buf, sizeof buf, fmt, detail ? detail : "");
+    c->last_error = buf;
+}
+
+void hip_check(sline_ctx *c, hipError_t e, const char *where) {
+    if (e == hipSuccess) return;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    c->last_error = buf;
+    throw Fail{SLINE_EDEVICE};
+}
+
+void *dev_alloc(sline_ctx *c, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, (void *)c->stream, c->alloc.user);
+    } else {
+        if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+    }
+    return p;
+}
+
+void dev_free(sline_ctx *c, void *p, size_t bytes) {
+    if (!p) return;
+    if (c->has_alloc) c->alloc.free(p, bytes, (void *)c->stream, c->alloc.user);
+    else (void)hipFreeAsync(p, c->stream);
+}
+
+// Bump allocator over the context workspace.
+struct Arena {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename T>
+    T *take(int64_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+        return p;
+    }
+};
+
+void ensure_ws(sline_ctx *c, size_t bytes) {
+    if (c->ws_bytes >= bytes) return;
+    if (c->ws) {
+        hip_check(c, hipStreamSynchronize(c->stream), "workspace release");
+        dev_free(c, c->ws, c->ws_bytes);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    c->ws = dev_alloc(c, want);
+    if (!c->ws) {
+        set_err(c, "workspace allocation of %s bytes failed", std::to_string(want).c_str());
+        throw Fail{SLINE_ENOMEM};
+    }
+    c->ws_bytes = want;
+}
+
+void sync(sline_ctx *c, const char *where) { hip_check(c, hipStreamSynchronize(c->stream), where); }
+
+struct Layout {
+    int32_t *err, *bins, *seg, *queue;
+    int64_t *totals, *passes;
+    int32_t *rowid, *degT, *ptrT, *fillT, *colT, *mid_list, *big_list;
+    int32_t *ptrS, *cntS, *itmS;
+    int64_t *cost, *rowoff, *part64;
+    int32_t *part32, *small_list, *heavy_list, *rowcnt, *cur, *nxt;
+};
+
+Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64_t M, bool filt) {
+    Layout L{};
+    L.err = A.take<int32_t>(4);
+    L.bins = A.take<int32_t>(130);
+    L.seg = A.take<int32_t>(4);
+    L.queue = A.take<int32_t>(4);
+    L.totals = A.take<int64_t>(4);
+    L.passes = A.take<int64_t>(2);
+    L.rowid = A.take<int32_t>(nnz);
+    L.degT = A.take<int32_t>(n);
+    L.ptrT = A.take<int32_t>(n + 1);
+    L.fillT = A.take<int32_t>(n);
+    L.colT = A.take<int32_t>(nnz);
+    L.mid_list = A.take<int32_t>(n);
+    L.big_list = A.take<int32_t>(n);
+    const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m}) + 1);
+    L.part32 = A.take<int32_t>(pmax);
+    L.part64 = A.take<int64_t>(pmax);
+    if (filt) {
+        L.ptrS = A.take<int32_t>(M + 1);
+        L.cntS = A.take<int32_t>(M);
+        L.itmS = A.take<int32_t>(nnz);
+    }
+    L.cost = A.take<int64_t>(N);
+    L.small_list = A.take<int32_t>(N);
+    L.heavy_list = A.take<int32_t>(N);
+    L.rowcnt = A.take<int32_t>(N);
+    L.rowoff = A.take<int64_t>(N + 1);
+    L.cur = A.take<int32_t>(nnz);
+    L.nxt = A.take<int32_t>(nnz);
+    return L;
+}
+
+void transpose(sline_ctx *c, const Layout &L, const int32_t *col, int32_t n, int64_t nnz) {
+    hipStream_t st = c->stream;
+    hip_check(c, launch_fill_i32(st, L.degT, n, 0), "zero degrees");
+    hip_check(c, launch_fill_i32(st, L.fillT, n, 0), "zero cursors");
+    hip_check(c, launch_degree(st, col, nnz, n, L.degT), "degree");
+    hip_check(c, launch_scan_i32(st, L.degT, n, L.ptrT, L.part32), "transpose scan");
+    hip_check(c, launch_scatter(st, col, L.rowid, nnz, n, L.ptrT, L.fillT, L.colT), "scatter");
+    hip_check(c, launch_segsort_classify(st, L.ptrT, n, L.mid_list, L.big_list, L.seg), "classify rows");
+    hip_check(c, launch_segsort_small(st, L.ptrT, n, L.colT), "sort short rows");
+    hip_check(c, launch_segsort_mid(st, L.ptrT, L.mid_list, L.seg, std::max(1, c->n_cu * 8), L.colT),
+              "sort rows in LDS");
+    hip_check(c, hipMemcpyAsync(c->host, L.seg, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+              "read row classes");
+    sync(c, "transpose");
+    const int32_t *hs = reinterpret_cast<const int32_t *>(c->host);
+    const int32_t nbig = hs[1], maxdeg = hs[2];
+    if (nbig == 0) return;
+    // rows longer than the LDS sort: bitonic network in global memory, one row at a time
+    int32_t n2 = 1;
+    while (n2 < maxdeg) n2 <<= 1;
+    int32_t *big = (int32_t *)malloc(sizeof(int32_t) * (size_t)nbig);
+    int32_t *bptr = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)nbig);
+    if (!big || !bptr) {
+        free(big);
+        free(bptr);
+        set_err(c, "host allocation failed");
+        throw Fail{SLINE_ENOMEM};
+    }
+    int32_t *tmp = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)n2);
+    if (!tmp) {
+        free(big);
+        free(bptr);
+        set_err(c, "device allocation failed (long-row sort)");
+        throw Fail{SLINE_ENOMEM};
+    }
+    try {
+        hip_check(c, hipMemcpyAsync(big, L.big_list, sizeof(int32_t) * nbig, hipMemcpyDeviceToHost, st),
+                  "read long rows");
+        sync(c, "read long rows");
+        for (int32_t q = 0; q < nbig; ++q) {
+            hip_check(c, hipMemcpyAsync(bptr + 2 * q, L.ptrT + big[q], 2 * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st),
+                      "read long row bounds");
+        }
+        sync(c, "read long row bounds");
+        for (int32_t q = 0; q < nbig; ++q) {
+            const int32_t b = bptr[2 * q], len = bptr[2 * q + 1] - b;
+            int32_t m2 = 1;
+            while (m2 < len) m2 <<= 1;
+            hip_check(c, launch_segsort_big_load(st, L.colT + b, len, m2, tmp), "long row load");
+            for (int32_t k = 2; k <= m2; k <<= 1)
+                for (int32_t j = k >> 1; j > 0; j >>= 1)
+                    hip_check(c, launch_bitonic_step(st, tmp, m2, k, j), "long row sort");
+            hip_check(c, launch_segsort_big_store(st, tmp, len, L.colT + b), "long row store");
+        }
+        sync(c, "long row sort");
+    } catch (...) {
+        dev_free(c, tmp, sizeof(int32_t) * (size_t)n2);
+        free(big);
+        free(bptr);
+        throw;
+    }
+    dev_free(c, tmp, sizeof(int32_t) * (size_t)n2);
+    free(big);
+    free(bptr);
+}
+
+bool same_call(const sline_ctx::Pending &p, const sline_csr &H, int32_t s, int32_t dual,
+               uint32_t flags) {
+    return p.valid && p.H.row_ptr == H.row_ptr && p.H.col_idx == H.col_idx &&
+           p.H.n_edges == H.n_edges && p.H.n_vertices == H.n_vertices && p.s == s &&
+           p.dual == dual && p.flags == flags;
+}
+
+void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
+    int32_t *a = out->a, *b = out->b, *w = out->w;
+    bool owned = false;
+    if (out->capacity == 0 && total > 0) {
+        const size_t bytes = sizeof(int32_t) * (size_t)total;
+        a = (int32_t *)dev_alloc(c, bytes);
+        b = a ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+        w = b ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+        if (!w) {
+            dev_free(c, a, bytes);
+            dev_free(c, b, bytes);
+            set_err(c, "output allocation of %s pairs failed", std::to_string(total).c_str());
+            throw Fail{SLINE_ENOMEM};
+        }
+        owned = true;
+    }
+    if (total > 0) {
+        CountArgs F = c->fill_args;
+        F.out_a = a;
+        F.out_b = b;
+        F.out_w = w;
+        try {
+            hip_check(c, launch_count(c->stream, F), "fill pass");
+            sync(c, "fill pass");
+        } catch (...) {
+            if (owned) {
+                const size_t bytes = sizeof(int32_t) * (size_t)total;
+                dev_free(c, a, bytes);
+                dev_free(c, b, bytes);
+                dev_free(c, w, bytes);
+            }
+            throw;
+        }
+    }
+    if (out->capacity == 0) {
+        out->a = owned ? a : nullptr;
+        out->b = owned ? b : nullptr;
+        out->w = owned ? w : nullptr;
+    }
+    out->n_pairs = total;
+}
+
+sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
+                        sline_edges *out) {
+    if (!out) {
+        set_err(c, "out is NULL");
+        return SLINE_EINVAL;
+    }
+    if (s < 1 || (dual != 0 && dual != 1) || H.n_edges < 0 || H.n_vertices < 0) {
+        set_err(c, "invalid argument (s >= 1, dual in {0,1}, sizes >= 0 required)");
+        return SLINE_EINVAL;
+    }
+    if (out->capacity < 0 || (out->capacity > 0 && (!out->a || !out->b || !out->w))) {
+        set_err(c, "output buffers: capacity > 0 requires a, b and w");
+        return SLINE_EINVAL;
+    }
+    if (same_call(c->pending, H, s, dual, flags)) {
+        const int64_t total = c->pending.total;
+        if (out->capacity > 0 && out->capacity < total) {
+            out->n_pairs = total;
+            set_err(c, "capacity too small");
+            return SLINE_ECAPACITY;
+        }
+        c->pending.valid = false;
+        run_fill(c, out, total);
+        c->stats.n_pairs = total;
+        return SLINE_OK;
+    }
+    c->pending.valid = false;
+
+    const int64_t m = H.n_edges, n = H.n_vertices;
+    if (m > 0 && !H.row_ptr) {
+        set_err(c, "row_ptr is NULL");
+        return SLINE_EINVAL;
+    }
+    hipStream_t st = c->stream;
+    sline_stats S{};
+    S.n_items = dual ? n : m;
+    int64_t nnz = 0;
+    // 1. row_ptr check and nnz
+    {
+        ensure_ws(c, 4096);
+        int32_t *err = reinterpret_cast<int32_t *>(c->ws);
+        hip_check(c, launch_fill_i32(st, err, 4, 0), "zero flags");
+        if (m > 0) {
+            hip_check(c, launch_check_rowptr(st, H.row_ptr, (int32_t)m, err), "row_ptr check");
+            hip_check(c, hipMemcpyAsync(c->host, H.row_ptr + m, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                      "read nnz");
+        } else {
+            reinterpret_cast<int32_t *>(c->host)[0] = 0;
+        }
+        hip_check(c, hipMemcpyAsync(reinterpret_cast<int32_t *>(c->host) + 1, err, sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "row_ptr check");
+        const int32_t *hp = reinterpret_cast<const int32_t *>(c->host);
+        nnz = hp[0];
+        if (hp[1] != 0 || nnz < 0) {
+            set_err(c, "row_ptr must start at 0 and never decrease");
+            return SLINE_EINVAL;
+        }
+        if (nnz > 0 && !H.col_idx) {
+            set_err(c, "col_idx is NULL with nnz > 0");
+            return SLINE_EINVAL;
+        }
+        if (nnz > 0 && n == 0) {
+            set_err(c, "members present but n_vertices = 0");
+            return SLINE_EINVAL;
+        }
+    }
+    S.nnz = nnz;
+    const int64_t N = dual ? n : m;
+    const int64_t M = dual ? m : n;
+    if (nnz == 0) {
+        // no item has a member, so no two items overlap
+        c->stats = S;
+        out->n_pairs = 0;
+        if (out->capacity == 0) out->a = out->b = out->w = nullptr;
+        return SLINE_OK;
+    }
+    const bool filt = s > 1;
+    Arena sizing;
+    plan_layout(sizing, m, n, nnz, N, M, filt);
+    ensure_ws(c, sizing.off + 4096);
+    Arena A;
+    A.base = reinterpret_cast<char *>(c->ws);
+    const Layout L = plan_layout(A, m, n, nnz, N, M, filt);
+
+    hip_check(c, launch_fill_i32(st, L.err, 4, 0), "zero flags");
+    hip_check(c, launch_fill_i32(st, L.bins, 130, 0), "zero bins");
+    hip_check(c, launch_fill_i32(st, L.seg, 4, 0), "zero classes");
+    hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
+    hip_check(c, launch_fill_i64(st, L.passes, 2, 0), "zero passes");
+    hip_check(c, launch_fill_i32(st, L.rowcnt, N, 0), "zero counts");
+
+    // 2. row ids and member checks (range checks always: they guard every later index)
+    hip_check(c, launch_rows(st, H.row_ptr, H.col_idx, (int32_t)m, (int32_t)n, nnz,
+                             (flags & SLINE_SKIP_VALIDATE) ? 0 : 1, L.rowid, L.err),
+              "row check");
+    // 3. transpose (bad members are skipped by every kernel and reported below)
+    transpose(c, L, H.col_idx, (int32_t)n, nnz);
+    hip_check(c, hipMemcpyAsync(c->host, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "member check");
+    if (reinterpret_cast<const int32_t *>(c->host)[0] & (kErrColRange | kErrColOrder)) {
+        set_err(c, "col_idx: members must lie in [0, n_vertices) and increase strictly within a row");
+        return SLINE_EINVAL;
+    }
+    // 4. roles
+    const int32_t *ptrI = dual ? L.ptrT : H.row_ptr;
+    const int32_t *memI = dual ? L.colT : H.col_idx;
+    const int32_t *ptrM = dual ? H.row_ptr : L.ptrT;
+    const int32_t *itmM = dual ? H.col_idx : L.colT;
+    // 5. s filter
+    const int32_t *ptrS = ptrM, *itmS = itmM;
+    if (filt) {
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, nullptr, L.cntS, nullptr),
+                  "filter count");
+        hip_check(c, launch_scan_i32(st, L.cntS, M, L.ptrS, L.part32), "filter scan");
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, L.ptrS, L.cntS, L.itmS),
+                  "filter fill");
+        ptrS = L.ptrS;
+        itmS = L.itmS;
+    }
+    // 6. wedge counts and buckets
+    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, ptrS, itmS, L.cost, L.totals), "cost");
+    hip_check(c, launch_classify(st, L.cost, (int32_t)N, c->tune.small_max_wedges, L.small_list,
+                                 L.heavy_list, L.bins),
+              "buckets");
+    // 7. count pass
+    CountArgs C{};
+    C.ptrI = ptrI;
+    C.memI = memI;
+    C.ptrS = ptrS;
+    C.itmS = itmS;
+    C.N = (int32_t)N;
+    C.s = s;
+    C.cost = L.cost;
+    C.small_list = L.small_list;
+    C.heavy_list = L.heavy_list;
+    C.bins = L.bins;
+    C.queue = L.queue;
+    C.cur = L.cur;
+    C.nxt = L.nxt;
+    C.rowcnt = L.rowcnt;
+    C.rowoff = nullptr;
+    C.passes = L.passes;
+    C.err = L.err;
+    C.tune = c->tune;
+    C.n_cu = c->n_cu;
+    hip_check(c, launch_count(st, C), "count pass");
+    hip_check(c, launch_scan_i32_to_i64(st, L.rowcnt, N, L.rowoff, L.part64), "pair scan");
+    int64_t *h = c->host;
+    hip_check(c, hipMemcpyAsync(h + 0, L.rowoff + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read total");
+    hip_check(c, hipMemcpyAsync(h + 1, L.totals, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st), "read totals");
+    hip_check(c, hipMemcpyAsync(h + 4, L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read passes");
+    hip_check(c, hipMemcpyAsync(h + 5, L.bins + 128, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read bins");
+    hip_check(c, hipMemcpyAsync(h + 6, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "count pass");
+    const int64_t total = h[0];
+    const int32_t *hb = reinterpret_cast<const int32_t *>(h + 5);
+    S.n_kept = h[1];
+    S.nnz_kept = h[2];
+    S.wedges = h[3];
+    S.passes = h[4];
+    S.n_small = hb[0];
+    S.n_heavy = hb[1];
+    S.n_pairs = total;
+    if (reinterpret_cast<const int32_t *>(h + 6)[0] & kErrInternal) {
+        set_err(c, "internal error: counting table overflow");
+        return SLINE_EDEVICE;
+    }
+    c->stats = S;
+    C.rowoff = L.rowoff;
+    C.passes = nullptr;
+    c->fill_args = C;
+    c->fill_total = total;
+    if (out->capacity > 0 && out->capacity < total) {
+        c->pending.valid = true;
+        c->pending.H = H;
+        c->pending.s = s;
+        c->pending.dual = dual;
+        c->pending.flags = flags;
+        c->pending.total = total;
+        out->n_pairs = total;
+        set_err(c, "capacity too small");
+        return SLINE_ECAPACITY;
+    }
+    // 8. fill
+    run_fill(c, out, total);
+    return SLINE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const sline_allocator *alloc) {
+    if (!ctx) return SLINE_EINVAL;
+    *ctx = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return SLINE_EINVAL;
+    sline_ctx *c = new (std::nothrow) sline_ctx();
+    if (!c) return SLINE_ENOMEM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (alloc) {
+        c->alloc = *alloc;
+        c->has_alloc = true;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SLINE_EDEVICE;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->n_cu = ncu;
+    if (hipHostMalloc((void **)&c->host, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SLINE_EDEVICE;
+    }
+    *ctx = c;
+    return SLINE_OK;
+}
+
+void sline_destroy(sline_ctx *c) {
+    if (!c) return;
+    if (c->ws) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(c, c->ws, c->ws_bytes);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    if (c->host) (void)hipHostFree(c->host);
+    delete c;
+}
+
+sline_status sline_build(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uint32_t flags,
+                         sline_edges *out) {
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return build_impl(c, H, s, dual, flags, out);
+    } catch (const Fail &f) {
+        c->pending.valid = false;
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        c->pending.valid = false;
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_edges_free(sline_ctx *c, sline_edges *e) {
+    if (!c || !e) return SLINE_EINVAL;
+    if (e->capacity == 0) {
+        const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(e->n_pairs, 0);
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(c, e->a, bytes);
+        dev_free(c, e->b, bytes);
+        dev_free(c, e->w, bytes);
+        (void)hipStreamSynchronize(c->stream);
+        e->a = e->b = e->w = nullptr;
+        e->n_pairs = 0;
+    }
+    return SLINE_OK;
+}
+
+sline_status sline_last_stats(sline_ctx *c, sline_stats *s) {
+    if (!c || !s) return SLINE_EINVAL;
+    *s = c->stats;
+    return SLINE_OK;
+}
+
+const char *sline_status_str(sline_status s) {
+    switch (s) {
+        case SLINE_OK: return "ok";
+        case SLINE_EINVAL: return "invalid argument";
+        case SLINE_ENOMEM: return "out of memory";
+        case SLINE_ECAPACITY: return "output capacity too small";
+        case SLINE_EDEVICE: return "device error";
+        case SLINE_EBUSY: return "not ready";
+        default: return "unknown status";
+    }
+}
+
+const char *sline_last_error(sline_ctx *c) { return c ? c->last_error.c_str() : "no context"; }
+
+}  // extern "C"

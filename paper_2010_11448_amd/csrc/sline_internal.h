@@ -1,0 +1,115 @@
+// Internal declarations shared by the host side and the device kernels of
+// libsline.  Not installed; the public interface is include/sline.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sl {
+
+constexpr int kWave = 64;
+constexpr int32_t kEmpty = -1;
+
+// Error bits accumulated on the device while checking the input CSR.
+enum : int32_t {
+    kErrRowPtr0 = 1,      // row_ptr[0] != 0
+    kErrRowPtrOrder = 2,  // row_ptr decreases
+    kErrColRange = 4,     // a member outside [0, n_vertices)
+    kErrColOrder = 8,     // a row that is not strictly increasing
+    kErrInternal = 16,    // a table probe that found no room (never expected)
+};
+
+// Tunable launch parameters of the counting kernels (the autotuner sets them).
+struct Tuning {
+    int32_t small_max_wedges = 512;  // items with W_a up to this go to the one-wave kernel
+    int32_t light_len = 8;           // member runs up to this are walked by one lane
+    int32_t small_grid_per_cu = 16;  // one-wave workgroups per CU for the small kernel
+    int32_t heavy_grid_per_cu = 4;   // resident workgroups per CU for the heavy kernel
+    int32_t heavy_load_pct = 45;     // target table load of a heavy pass, percent
+};
+
+// Scan tile: 256 threads x 8 items.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Transposed rows up to this many entries are sorted in LDS.
+constexpr int kSegSortLds = 16384;
+constexpr int kSegSortSmall = 32;
+
+// Table sizes (slots) of the counting kernels.
+constexpr int kSmallSlots = 1024;
+constexpr int kHeavySlots = 4096;
+constexpr int kHeavyThreads = 256;
+
+// ------------------------------------------------------------ launchers
+// Every launcher enqueues on `st` and returns the launch status.
+
+hipError_t launch_check_rowptr(hipStream_t st, const int32_t *rp, int32_t m, int32_t *err);
+hipError_t launch_rows(hipStream_t st, const int32_t *rp, const int32_t *col, int32_t m,
+                       int32_t n, int64_t nnz, int check_order, int32_t *rowid, int32_t *err);
+hipError_t launch_degree(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
+                         int32_t *deg);
+hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v);
+hipError_t launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
+hipError_t launch_copy_i32(hipStream_t st, int32_t *dst, const int32_t *src, int64_t n);
+
+// Exclusive scan: out[0..n] with out[n] = total.  `partial` needs
+// scan_partials(n) entries of the accumulator type.
+int64_t scan_partials(int64_t n);
+hipError_t launch_scan_i32(hipStream_t st, const int32_t *in, int64_t n, int32_t *out,
+                           int32_t *partial);
+hipError_t launch_scan_i32_to_i64(hipStream_t st, const int32_t *in, int64_t n, int64_t *out,
+                                  int64_t *partial);
+
+hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *rowid, int64_t nnz,
+                          int32_t n, const int32_t *ptrT, int32_t *fill, int32_t *colT);
+// Sorts every transposed row ascending.  `counts` holds 3 int32 (mid, big,
+// max degree), `mid_list`/`big_list` hold up to n entries each.
+hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
+                                   int32_t *mid_list, int32_t *big_list, int32_t *counts);
+hipError_t launch_segsort_small(hipStream_t st, const int32_t *ptr, int32_t n, int32_t *val);
+hipError_t launch_segsort_mid(hipStream_t st, const int32_t *ptr, const int32_t *mid_list,
+                              const int32_t *counts, int32_t grid, int32_t *val);
+hipError_t launch_segsort_big_load(hipStream_t st, const int32_t *src, int32_t len, int32_t n2,
+                                   int32_t *tmp);
+hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t k, int32_t j);
+hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
+                                    int32_t *dst);
+
+// Filtered membership lists N_s(v): the items of v's list with size >= s.
+hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
+                         const int32_t *ptrI, int32_t s, const int32_t *ptrS, int32_t *cntS,
+                         int32_t *itmS);
+
+// Per-item exact wedge count W_a and the run totals.
+// totals[0] = kept items, [1] = kept incidences, [2] = wedges.
+hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
+                       int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
+                       int64_t *totals);
+
+// Buckets: small list (one-wave kernel) and heavy list ordered by descending
+// log2(W_a).  `bins` holds 64 counters + 64 cursors + 2 totals (int32).
+hipError_t launch_classify(hipStream_t st, const int64_t *cost, int32_t N, int32_t small_max,
+                           int32_t *small_list, int32_t *heavy_list, int32_t *bins);
+
+struct CountArgs {
+    const int32_t *ptrI, *memI;  // item lists
+    const int32_t *ptrS, *itmS;  // filtered membership lists
+    int32_t N, s;
+    const int64_t *cost;
+    const int32_t *small_list, *heavy_list;
+    const int32_t *bins;         // n_small at bins[128], n_heavy at bins[129]
+    int32_t *queue;              // heavy work-queue head (reset by the launcher)
+    int32_t *cur, *nxt;          // per item-incidence cursors (heavy kernel)
+    int32_t *rowcnt;             // count mode: pairs per item
+    const int64_t *rowoff;       // fill mode: output offset per item (nullptr = count mode)
+    int32_t *out_a, *out_b, *out_w;
+    int64_t *passes;
+    int32_t *err;
+    Tuning tune;
+    int32_t n_cu;
+};
+hipError_t launch_count(hipStream_t st, const CountArgs &a);
+
+}  // namespace sl

@@ -1,0 +1,556 @@
+// Preparation kernels of libsline for gfx950: CSR checks, degree histogram,
+// device-wide exclusive scans, the transpose (atomic scatter followed by a
+// per-row sort), the s-filtered membership lists, the exact per-item wedge
+// count W_a and the degree buckets.
+//
+// The transpose turns the hyperedge -> vertex incidence lists into vertex ->
+// hyperedge lists (the other side of the bipartite representation, Sec. III);
+// with both adjacencies the counting kernels walk, for an item a, only the
+// items that share a member with it (Sec. IV-B).  Item sizes |S_a| drive the
+// degree-based pruning of Sec. IV-C.
+#include "sline_internal.h"
+
+namespace sl {
+
+namespace {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across a 256-thread block; returns the exclusive prefix of
+// `v` and writes the block total to `total`.
+template <typename T>
+__device__ T block_excl_scan(T v, T *sh /* 4 + 1 */, T &total) {
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    T inc = wave_incl_scan(v);
+    if (lane == kWave - 1) sh[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
+            T t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[kScanThreads / kWave] = run;
+    }
+    __syncthreads();
+    T ex = sh[wid] + inc - v;
+    total = sh[kScanThreads / kWave];
+    __syncthreads();
+    return ex;
+}
+
+// first index p in [lo, hi) with arr[p] > key (arr ascending), hi if none
+__device__ __forceinline__ int32_t upper_bound(const int32_t *arr, int32_t lo, int32_t hi,
+                                               int32_t key) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (arr[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ------------------------------------------------------------- checks
+
+__global__ void k_check_rowptr(const int32_t *rp, int32_t m, int32_t *err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && rp[0] != 0) atomicOr(err, kErrRowPtr0);
+    if (i < m && rp[i] > rp[i + 1]) atomicOr(err, kErrRowPtrOrder);
+}
+
+// One wave per row (grid-stride): the row id of every incidence, member range
+// checks and, when asked, the strictly-increasing check of each row.
+__global__ __launch_bounds__(256) void k_rows(const int32_t *rp, const int32_t *col, int32_t m,
+                                              int32_t n, int64_t nnz, int check_order,
+                                              int32_t *rowid, int32_t *err) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    int32_t bad = 0;
+    for (int64_t i = wave; i < m; i += nwaves) {
+        int64_t b = rp[i], e = rp[i + 1];
+        if (b < 0) b = 0;
+        if (e > nnz) e = nnz;
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            int32_t v = col[k];
+            rowid[k] = (int32_t)i;
+            if (v < 0 || v >= n) bad |= kErrColRange;
+            if (check_order && k + 1 < e && col[k + 1] <= v) bad |= kErrColOrder;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_degree(const int32_t *col, int64_t nnz, int32_t n, int32_t *deg) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = col[k];
+        if (v >= 0 && v < n) atomicAdd(&deg[v], 1);
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_copy(int32_t *dst, const int32_t *src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// --------------------------------------------------------------- scan
+// Three phases: per-tile sums, one-block scan of the tile sums, per-tile
+// scan plus tile offset.  out has n + 1 entries; out[n] is the total.
+
+template <typename TI, typename TA>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const TI *in, int64_t n,
+                                                              TA *partial) {
+    __shared__ TA sh[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TA s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < n) s += (TA)in[base + q];
+    TA tot;
+    block_excl_scan<TA>(s, sh, tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+template <typename TA>
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(TA *partial, int64_t nb) {
+    __shared__ TA sh[kScanThreads / kWave + 1];
+    TA carry = 0;
+    for (int64_t c = 0; c < nb; c += kScanTile) {
+        const int64_t base = c + (int64_t)threadIdx.x * kScanItems;
+        TA v[kScanItems];
+        TA s = 0;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            v[q] = (base + q < nb) ? partial[base + q] : (TA)0;
+            s += v[q];
+        }
+        TA tot;
+        TA ex = block_excl_scan<TA>(s, sh, tot);
+        TA run = carry + ex;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            if (base + q < nb) partial[base + q] = run;
+            run += v[q];
+        }
+        carry += tot;
+    }
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const TI *in, int64_t n,
+                                                            const TO *partial, TO *out) {
+    __shared__ TO sh[kScanThreads / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TO v[kScanItems];
+    TO s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = (base + q < n) ? (TO)in[base + q] : (TO)0;
+        s += v[q];
+    }
+    TO tot;
+    TO ex = block_excl_scan<TO>(s, sh, tot);
+    TO run = partial[blockIdx.x] + ex;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[blockIdx.x] + tot;
+}
+
+template <typename TO>
+__global__ void k_zero_total(TO *out) { out[0] = 0; }
+
+// ---------------------------------------------------------- transpose
+
+__global__ void k_scatter(const int32_t *col, const int32_t *rowid, int64_t nnz, int32_t n,
+                          const int32_t *ptrT, int32_t *fill, int32_t *colT) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = col[k];
+        if (v < 0 || v >= n) continue;
+        int32_t p = ptrT[v] + atomicAdd(&fill[v], 1);
+        colT[p] = rowid[k];
+    }
+}
+
+__global__ void k_segsort_classify(const int32_t *ptr, int32_t n, int32_t *mid_list,
+                                   int32_t *big_list, int32_t *counts) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        int32_t d = ptr[v + 1] - ptr[v];
+        if (d > kSegSortSmall && d <= kSegSortLds) mid_list[atomicAdd(&counts[0], 1)] = (int32_t)v;
+        else if (d > kSegSortLds) {
+            big_list[atomicAdd(&counts[1], 1)] = (int32_t)v;
+            atomicMax(&counts[2], d);
+        }
+    }
+}
+
+// Rows of up to kSegSortSmall entries: one thread, insertion sort in place.
+__global__ void k_segsort_small(const int32_t *ptr, int32_t n, int32_t *val) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = ptr[v], d = ptr[v + 1] - b;
+        if (d < 2 || d > kSegSortSmall) continue;
+        int32_t *x = val + b;
+        for (int32_t i = 1; i < d; ++i) {
+            int32_t key = x[i];
+            int32_t j = i - 1;
+            while (j >= 0 && x[j] > key) {
+                x[j + 1] = x[j];
+                --j;
+            }
+            x[j + 1] = key;
+        }
+    }
+}
+
+// Rows of kSegSortSmall < d <= kSegSortLds entries: one workgroup, bitonic
+// sort in LDS padded to a power of two.
+__global__ __launch_bounds__(256) void k_segsort_mid(const int32_t *ptr, const int32_t *mid_list,
+                                                     const int32_t *counts, int32_t *val) {
+    __shared__ int32_t buf[kSegSortLds];
+    const int32_t nmid = counts[0];
+    for (int32_t r = blockIdx.x; r < nmid; r += gridDim.x) {
+        const int32_t v = mid_list[r];
+        const int32_t b = ptr[v], d = ptr[v + 1] - b;
+        int32_t n2 = 1;
+        while (n2 < d) n2 <<= 1;
+        for (int32_t i = threadIdx.x; i < n2; i += blockDim.x)
+            buf[i] = (i < d) ? val[b + i] : INT32_MAX;
+        __syncthreads();
+        for (int32_t k = 2; k <= n2; k <<= 1) {
+            for (int32_t j = k >> 1; j > 0; j >>= 1) {
+                for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+                    int32_t l = i ^ j;
+                    if (l > i) {
+                        int32_t x = buf[i], y = buf[l];
+                        bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            buf[i] = y;
+                            buf[l] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int32_t i = threadIdx.x; i < d; i += blockDim.x) val[b + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+__global__ void k_big_load(const int32_t *src, int32_t len, int32_t n2, int32_t *tmp) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+         i += (int64_t)gridDim.x * blockDim.x)
+        tmp[i] = (i < len) ? src[i] : INT32_MAX;
+}
+
+__global__ void k_bitonic_step(int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t l = i ^ j;
+        if (l > i) {
+            int32_t x = tmp[i], y = tmp[l];
+            bool up = (i & k) == 0;
+            if ((x > y) == up) {
+                tmp[i] = y;
+                tmp[l] = x;
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------- s filtering
+
+// One wave per member list (grid-stride).  Pass 1 (itmS == nullptr) counts
+// the items of size >= s; pass 2 writes them, in list order, at ptrS[v].
+__global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32_t *itmM,
+                                                int32_t M, const int32_t *ptrI, int32_t s,
+                                                const int32_t *ptrS, int32_t *cntS,
+                                                int32_t *itmS) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t v = wave; v < M; v += nwaves) {
+        const int32_t b = ptrM[v], e = ptrM[v + 1];
+        int32_t run = itmS ? ptrS[v] : 0;
+        for (int32_t k0 = b; k0 < e; k0 += kWave) {
+            const int32_t k = k0 + lane;
+            bool keep = false;
+            int32_t it = 0;
+            if (k < e) {
+                it = itmM[k];
+                keep = (ptrI[it + 1] - ptrI[it]) >= s;
+            }
+            const uint64_t bal = __ballot(keep);
+            if (itmS && keep) itmS[run + lanes_below(bal)] = it;
+            run += __popcll(bal);
+        }
+        if (!itmS && lane == 0) cntS[v] = run;
+    }
+}
+
+// One wave per item (grid-stride): W_a = sum over members v of the number of
+// kept items b > a in N_s(v); 0 for items with |S_a| < s.
+__global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t *memI,
+                                              int32_t N, int32_t s, const int32_t *ptrS,
+                                              const int32_t *itmS, int64_t *cost,
+                                              int64_t *totals) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    int64_t kept = 0, kept_nnz = 0, wedges = 0;
+    for (int64_t a = wave; a < N; a += nwaves) {
+        const int32_t b = ptrI[a], e = ptrI[a + 1];
+        if (e - b < s) {
+            if (lane == 0) cost[a] = 0;
+            continue;
+        }
+        int64_t c = 0;
+        for (int32_t k = b + lane; k < e; k += kWave) {
+            const int32_t v = memI[k];
+            const int32_t lo = ptrS[v], hi = ptrS[v + 1];
+            c += hi - upper_bound(itmS, lo, hi, (int32_t)a);
+        }
+        c = wave_sum(c);
+        if (lane == 0) cost[a] = c;
+        kept += 1;
+        kept_nnz += e - b;
+        wedges += c;
+    }
+    if (lane == 0 && kept) {
+        atomicAdd((unsigned long long *)&totals[0], (unsigned long long)kept);
+        atomicAdd((unsigned long long *)&totals[1], (unsigned long long)kept_nnz);
+        atomicAdd((unsigned long long *)&totals[2], (unsigned long long)wedges);
+    }
+}
+
+// --------------------------------------------------------- buckets
+// bins[0..63]: heavy items per log2 bin; bins[64..127]: bin cursors;
+// bins[128]: small count; bins[129]: heavy count.
+
+__device__ __forceinline__ int log2_bin(int64_t c) { return 63 - __clzll((unsigned long long)c); }
+
+__global__ void k_classify_count(const int64_t *cost, int32_t N, int32_t small_max,
+                                 int32_t *small_list, int32_t *bins) {
+    __shared__ int32_t hist[64];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = cost[a];
+        if (c <= 0) continue;
+        if (c <= small_max) small_list[atomicAdd(&bins[128], 1)] = (int32_t)a;
+        else atomicAdd(&hist[log2_bin(c)], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64; i += blockDim.x)
+        if (hist[i]) atomicAdd(&bins[i], hist[i]);
+}
+
+// Cursors: bins processed from the most expensive (longest first).
+__global__ void k_classify_offsets(int32_t *bins) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int32_t run = 0;
+        for (int b = 63; b >= 0; --b) {
+            bins[64 + b] = run;
+            run += bins[b];
+        }
+        bins[129] = run;
+    }
+}
+
+__global__ void k_classify_scatter(const int64_t *cost, int32_t N, int32_t small_max,
+                                   int32_t *heavy_list, int32_t *bins) {
+    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = cost[a];
+        if (c <= small_max) continue;
+        heavy_list[atomicAdd(&bins[64 + log2_bin(c)], 1)] = (int32_t)a;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_check_rowptr(hipStream_t st, const int32_t *rp, int32_t m, int32_t *err) {
+    k_check_rowptr<<<grid_for((int64_t)m + 1, 256), 256, 0, st>>>(rp, m, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows(hipStream_t st, const int32_t *rp, const int32_t *col, int32_t m,
+                       int32_t n, int64_t nnz, int check_order, int32_t *rowid, int32_t *err) {
+    if (m <= 0) return hipSuccess;
+    k_rows<<<grid_for((int64_t)m * kWave, 256, 65536), 256, 0, st>>>(rp, col, m, n, nnz,
+                                                                    check_order, rowid, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_degree(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
+                         int32_t *deg) {
+    if (nnz <= 0) return hipSuccess;
+    k_degree<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(col, nnz, n, deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v) {
+    if (n <= 0) return hipSuccess;
+    k_fill<int32_t><<<grid_for(n, 256, 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v) {
+    if (n <= 0) return hipSuccess;
+    k_fill<int64_t><<<grid_for(n, 256, 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i32(hipStream_t st, int32_t *dst, const int32_t *src, int64_t n) {
+    if (n <= 0) return hipSuccess;
+    k_copy<<<grid_for(n, 256, 65536), 256, 0, st>>>(dst, src, n);
+    return hipGetLastError();
+}
+
+int64_t scan_partials(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <typename TI, typename TO>
+static hipError_t scan_impl(hipStream_t st, const TI *in, int64_t n, TO *out, TO *partial) {
+    if (n <= 0) {
+        k_zero_total<TO><<<1, 1, 0, st>>>(out);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    k_scan_reduce<TI, TO><<<(unsigned)nb, kScanThreads, 0, st>>>(in, n, partial);
+    k_scan_partials<TO><<<1, kScanThreads, 0, st>>>(partial, nb);
+    k_scan_down<TI, TO><<<(unsigned)nb, kScanThreads, 0, st>>>(in, n, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i32(hipStream_t st, const int32_t *in, int64_t n, int32_t *out,
+                           int32_t *partial) {
+    return scan_impl<int32_t, int32_t>(st, in, n, out, partial);
+}
+
+hipError_t launch_scan_i32_to_i64(hipStream_t st, const int32_t *in, int64_t n, int64_t *out,
+                                  int64_t *partial) {
+    return scan_impl<int32_t, int64_t>(st, in, n, out, partial);
+}
+
+hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *rowid, int64_t nnz,
+                          int32_t n, const int32_t *ptrT, int32_t *fill, int32_t *colT) {
+    if (nnz <= 0) return hipSuccess;
+    k_scatter<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(col, rowid, nnz, n, ptrT, fill, colT);
+    return hipGetLastError();
+}
+
+hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
+                                   int32_t *mid_list, int32_t *big_list, int32_t *counts) {
+    if (n <= 0) return hipSuccess;
+    k_segsort_classify<<<grid_for(n, 256, 65536), 256, 0, st>>>(ptr, n, mid_list, big_list,
+                                                                 counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_segsort_small(hipStream_t st, const int32_t *ptr, int32_t n, int32_t *val) {
+    if (n <= 0) return hipSuccess;
+    k_segsort_small<<<grid_for(n, 256, 65536), 256, 0, st>>>(ptr, n, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_segsort_mid(hipStream_t st, const int32_t *ptr, const int32_t *mid_list,
+                              const int32_t *counts, int32_t grid, int32_t *val) {
+    if (grid <= 0) return hipSuccess;
+    k_segsort_mid<<<grid, 256, 0, st>>>(ptr, mid_list, counts, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_segsort_big_load(hipStream_t st, const int32_t *src, int32_t len, int32_t n2,
+                                   int32_t *tmp) {
+    k_big_load<<<grid_for(n2, 256, 65536), 256, 0, st>>>(src, len, n2, tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
+    k_bitonic_step<<<grid_for(n2, 256, 65536), 256, 0, st>>>(tmp, n2, k, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
+                                    int32_t *dst) {
+    k_copy<<<grid_for(len, 256, 65536), 256, 0, st>>>(dst, tmp, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
+                         const int32_t *ptrI, int32_t s, const int32_t *ptrS, int32_t *cntS,
+                         int32_t *itmS) {
+    if (M <= 0) return hipSuccess;
+    k_filter<<<grid_for((int64_t)M * kWave, 256, 65536), 256, 0, st>>>(ptrM, itmM, M, ptrI, s,
+                                                                       ptrS, cntS, itmS);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
+                       int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
+                       int64_t *totals) {
+    if (N <= 0) return hipSuccess;
+    k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s, ptrS,
+                                                                     itmS, cost, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(hipStream_t st, const int64_t *cost, int32_t N, int32_t small_max,
+                           int32_t *small_list, int32_t *heavy_list, int32_t *bins) {
+    if (N <= 0) return hipSuccess;
+    const int g = grid_for(N, 256, 4096);
+    k_classify_count<<<g, 256, 0, st>>>(cost, N, small_max, small_list, bins);
+    k_classify_offsets<<<1, 64, 0, st>>>(bins);
+    k_classify_scatter<<<g, 256, 0, st>>>(cost, N, small_max, heavy_list, bins);
+    return hipGetLastError();
+}
+
+}  // namespace sl

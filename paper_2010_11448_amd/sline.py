@@ -1,0 +1,230 @@
+"""Python binding of libsline (include/sline.h) -- argument marshalling only.
+
+Every computation runs in the HIP library ``libsline.so`` built from
+``csrc/``; this module only passes pointers and sizes.  If the library is
+missing it raises -- there is no CPU fallback.  PyTorch supplies device memory
+(through the allocator callbacks of ``sline_allocator``) and the stream.
+
+Low-level names mirror the C-ABI (``sline_create``, ``sline_build``, ...);
+``Context`` wraps them for torch tensors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsline.so")
+
+SLINE_OK = 0
+SLINE_EINVAL = -1
+SLINE_ENOMEM = -2
+SLINE_ECAPACITY = -3
+SLINE_EDEVICE = -4
+SLINE_EBUSY = -5
+SLINE_SKIP_VALIDATE = 1
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class sline_csr(ctypes.Structure):
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("n_edges", ctypes.c_int32), ("n_vertices", ctypes.c_int32)]
+
+
+class sline_edges(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("capacity", ctypes.c_int64),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class sline_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("n_items", "nnz", "nnz_kept", "n_kept", "wedges", "n_pairs", "n_small",
+                 "n_heavy", "passes")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class sline_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class SlineError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_str(status)} ({status}): {message}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes); every name here is declared in include/sline.h
+SIGNATURES = {
+    "sline_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.POINTER(sline_allocator)]),
+    "sline_destroy": (None, [ctypes.c_void_p]),
+    "sline_build": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
+    "sline_edges_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
+    "sline_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_stats)]),
+    "sline_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "sline_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+}
+
+
+def load(path: str | None = None):
+    """Load libsline.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libsline is not built ({p} missing); run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().sline_status_str(status).decode()
+
+
+# ------------------------------------------------------- C-ABI mirrors
+
+def sline_create(device: int = 0, hip_stream: int | None = None,
+                 allocator: sline_allocator | None = None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    st = load().sline_create(ctypes.byref(ctx), device, hip_stream,
+                             ctypes.byref(allocator) if allocator is not None else None)
+    if st != SLINE_OK:
+        raise SlineError(st, "sline_create failed")
+    return ctx
+
+
+def sline_destroy(ctx) -> None:
+    load().sline_destroy(ctx)
+
+
+def sline_build(ctx, csr: sline_csr, s: int, dual: int, flags: int, out: sline_edges) -> int:
+    return load().sline_build(ctx, csr, s, dual, flags, ctypes.byref(out))
+
+
+def sline_edges_free(ctx, edges: sline_edges) -> int:
+    return load().sline_edges_free(ctx, ctypes.byref(edges))
+
+
+def sline_last_stats(ctx) -> sline_stats:
+    st = sline_stats()
+    load().sline_last_stats(ctx, ctypes.byref(st))
+    return st
+
+
+def sline_last_error(ctx) -> str:
+    return load().sline_last_error(ctx).decode()
+
+
+def sline_status_str(status: int) -> str:
+    return status_str(status)
+
+
+# --------------------------------------------------------- torch layer
+
+@dataclass
+class LineGraph:
+    """L_s as device tensors (int32): pairs (a[k], b[k]) with overlap w[k]."""
+
+    a: "object"
+    b: "object"
+    w: "object"
+
+    def __len__(self) -> int:
+        return int(self.a.shape[0])
+
+
+def torch_allocator(device: int):
+    """An sline_allocator backed by PyTorch's caching allocator."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, stream, user):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    alloc = sline_allocator(fa, ff, None)
+    alloc._keep = (fa, ff)  # keep the callbacks alive with the struct
+    return alloc
+
+
+class Context:
+    """A libsline context on one device and torch stream."""
+
+    def __init__(self, device: int = 0, stream=None, torch_memory: bool = True):
+        import torch
+        load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._alloc = torch_allocator(device) if torch_memory else None
+        self.ctx = sline_create(device, self.stream.cuda_stream, self._alloc)
+
+    def close(self) -> None:
+        if self.ctx:
+            sline_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def csr(row_ptr, col, n_vertices: int) -> sline_csr:
+        import torch
+        for t in (row_ptr, col):
+            if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("row_ptr and col must be contiguous int32 device tensors")
+        return sline_csr(row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                         int(row_ptr.numel()) - 1, int(n_vertices))
+
+    def build(self, row_ptr, col, n_vertices: int, s: int, dual: int = 0,
+              flags: int = 0) -> LineGraph:
+        """L_s(H) (or L_s(H*) with dual=1) as int32 device tensors sorted by (a, b)."""
+        import torch
+        H = self.csr(row_ptr, col, n_vertices)
+        dev = torch.device("cuda", self.device)
+        probe = torch.empty(3, dtype=torch.int32, device=dev)
+        out = sline_edges(0, 1, probe[0:1].data_ptr(), probe[1:2].data_ptr(), probe[2:3].data_ptr())
+        st = sline_build(self.ctx, H, s, dual, flags, out)
+        if st == SLINE_OK:
+            n = int(out.n_pairs)  # 0 or 1 pair: it sits in the probe buffers
+            return LineGraph(probe[0:n].clone(), probe[1:1 + n].clone(), probe[2:2 + n].clone())
+        if st != SLINE_ECAPACITY:
+            raise SlineError(st, sline_last_error(self.ctx))
+        n = int(out.n_pairs)
+        a = torch.empty(n, dtype=torch.int32, device=dev)
+        b = torch.empty(n, dtype=torch.int32, device=dev)
+        w = torch.empty(n, dtype=torch.int32, device=dev)
+        out = sline_edges(0, n, a.data_ptr(), b.data_ptr(), w.data_ptr())
+        st = sline_build(self.ctx, H, s, dual, flags, out)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return LineGraph(a, b, w)
+
+    def stats(self) -> dict:
+        return sline_last_stats(self.ctx).as_dict()

@@ -1,0 +1,186 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bar: bit-exact -- the output is integer (ids and overlaps), so every element
+of a, b and w must equal the oracle's, in the same canonical (a, b) order.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2010_11448_amd import gen
+
+from helpers import assert_same, check_canonical_torch, digest_torch, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2010_11448_amd import sline
+
+    assert torch.cuda.is_available()
+    c = sline.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    return torch.device("cuda", 0)
+
+
+def _check(ctx, dev, g, s, dual, what):
+    print(f"case: {what} m={g.n_edges} n={g.n_vertices} s={s} dual={dual}", flush=True)
+    rp, col = to_device(g, dev)
+    L = ctx.build(rp, col, g.n_vertices, s, dual)
+    ref, _ = oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, threads=8)
+    assert_same(L, ref, f"{what} s={s} dual={dual}")
+    return L
+
+
+@pytest.mark.parametrize("seed", gen.UNIFORM_SEEDS)
+@pytest.mark.parametrize("dual", [0, 1])
+def test_uniform_2000_all_s(ctx, dev, seed, dual):
+    g = gen.uniform_2000(seed)
+    for s in gen.UNIFORM_S:
+        _check(ctx, dev, g, s, dual, f"uniform_2000 seed={seed}")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_random_small_with_duplicates_and_empty_rows(ctx, dev, seed):
+    g = gen.random_small(60, 40, 12, seed)
+    for dual in (0, 1):
+        for s in (1, 2, 3, 5, 13):
+            _check(ctx, dev, g, s, dual, f"random_small seed={seed}")
+
+
+def test_planted_structures(ctx, dev):
+    sun = gen.sunflower(300, 6, 5, seed=3)
+    for s in (1, 5, 6, 7):
+        _check(ctx, dev, sun, s, 0, "sunflower")
+    nest = gen.nested_chain(40, 7, seed=4)
+    for s in (1, 7, 100, 200, 280, 281):
+        _check(ctx, dev, nest, s, 0, "nested")
+        _check(ctx, dev, nest, s, 1, "nested")
+    cp = gen.planted_copies(gen.uniform_hypergraph(200, 300, 4, 12, seed=9), 3, seed=10)
+    for s in (1, 4, 8, 12):
+        _check(ctx, dev, cp, s, 0, "copies")
+
+
+def test_powerlaw_scaled(ctx, dev):
+    """A 1/50-scale power-law graph: heavy items, hub members, many passes."""
+    g = gen.powerlaw_1m(scale=0.02)
+    for dual, ss in ((0, (1, 2, 4, 8, 16)), (1, (2, 8, 32))):
+        for s in ss:
+            print(f"case: powerlaw 0.02 s={s} dual={dual}", flush=True)
+            rp, col = to_device(g, dev)
+            L = ctx.build(rp, col, g.n_vertices, s, dual)
+            ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, threads=8)
+            assert_same(L, ref, f"powerlaw0.02 s={s} dual={dual}")
+
+
+def test_edge_cases(ctx, dev):
+    import torch
+    from paper_2010_11448_amd import sline
+
+    # no hyperedges
+    rp = torch.zeros(1, dtype=torch.int32, device=dev)
+    col = torch.zeros(0, dtype=torch.int32, device=dev)
+    assert len(ctx.build(rp, col, 5, 1, 0)) == 0
+    assert len(ctx.build(rp, col, 5, 1, 1)) == 0
+    # all rows empty
+    rp = torch.zeros(4, dtype=torch.int32, device=dev)
+    assert len(ctx.build(rp, col, 3, 1, 0)) == 0
+    # one item
+    g = gen.from_sets([[0, 1, 2]], 3)
+    _check(ctx, dev, g, 1, 0, "single")
+    _check(ctx, dev, g, 1, 1, "single dual")
+    # s above every size
+    g = gen.uniform_2000(11)
+    rpd, cold = to_device(g, dev)
+    assert len(ctx.build(rpd, cold, g.n_vertices, 21, 0)) == 0
+    # identical rows
+    g = gen.from_sets([[1, 3, 5]] * 5 + [[0], []], 6)
+    for s in (1, 3, 4):
+        _check(ctx, dev, g, s, 0, "identical")
+        _check(ctx, dev, g, s, 1, "identical dual")
+
+
+def test_invalid_inputs(ctx, dev):
+    import torch
+    from paper_2010_11448_amd import sline
+
+    def bad(rp, col, n, s=1, dual=0):
+        with pytest.raises(sline.SlineError) as ei:
+            ctx.build(torch.tensor(rp, dtype=torch.int32, device=dev),
+                      torch.tensor(col, dtype=torch.int32, device=dev), n, s, dual)
+        assert ei.value.status == sline.SLINE_EINVAL
+
+    bad([0, 2, 4], [0, 1, 1, 1], 3)           # repeated member in a row
+    bad([0, 2, 4], [1, 0, 0, 2], 3)           # decreasing row
+    bad([0, 2, 4], [0, 3, 0, 1], 3)           # member out of range
+    bad([0, 2, 4], [0, -1, 0, 1], 3)          # negative member
+    bad([1, 2, 4], [0, 1, 0, 1], 3)           # row_ptr[0] != 0
+    bad([0, 3, 2], [0, 1, 2], 3)              # decreasing row_ptr
+    bad([0, 1, 2], [0, 1], 2, s=0)            # s < 1
+    bad([0, 1, 2], [0, 1], 2, dual=2)         # bad dual flag
+
+
+def test_capacity_protocol(ctx, dev):
+    """ECAPACITY reports the size and a retry writes the same result."""
+    import torch
+    from paper_2010_11448_amd import sline
+
+    g = gen.uniform_2000(12)
+    rp, col = to_device(g, dev)
+    H = sline.Context.csr(rp, col, g.n_vertices)
+    small = torch.zeros(3 * 10, dtype=torch.int32, device=dev)
+    out = sline.sline_edges(0, 10, small[0:10].data_ptr(), small[10:20].data_ptr(),
+                            small[20:30].data_ptr())
+    st = sline.sline_build(ctx.ctx, H, 1, 0, 0, out)
+    assert st == sline.SLINE_ECAPACITY
+    need = int(out.n_pairs)
+    ref, _ = oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, 1)
+    assert need == len(ref)
+    buf = torch.zeros(3 * need, dtype=torch.int32, device=dev)
+    out = sline.sline_edges(0, need, buf[0:need].data_ptr(), buf[need:2 * need].data_ptr(),
+                            buf[2 * need:].data_ptr())
+    assert sline.sline_build(ctx.ctx, H, 1, 0, 0, out) == sline.SLINE_OK
+    L = sline.LineGraph(buf[0:need], buf[need:2 * need], buf[2 * need:])
+    assert_same(L, ref, "capacity retry")
+    # library-allocated output, freed by the library
+    out = sline.sline_edges(0, 0, None, None, None)
+    assert sline.sline_build(ctx.ctx, H, 2, 0, 0, out) == sline.SLINE_OK
+    assert out.n_pairs == oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, 2)[1].n_pairs
+    assert sline.sline_edges_free(ctx.ctx, out) == sline.SLINE_OK
+    assert out.a is None and out.n_pairs == 0
+
+
+def test_deterministic_repeat(ctx, dev):
+    g = gen.powerlaw_1m(scale=0.01)
+    rp, col = to_device(g, dev)
+    for s, dual in ((1, 0), (2, 1)):
+        L1 = ctx.build(rp, col, g.n_vertices, s, dual)
+        L2 = ctx.build(rp, col, g.n_vertices, s, dual)
+        import torch
+        assert torch.equal(L1.a, L2.a) and torch.equal(L1.b, L2.b) and torch.equal(L1.w, L2.w)
+        check_canonical_torch(L1.a, L1.b, L1.w, s)
+
+
+def test_stats_match_oracle(ctx, dev):
+    g = gen.powerlaw_1m(scale=0.01)
+    rp, col = to_device(g, dev)
+    for s, dual in ((1, 0), (4, 0), (2, 1)):
+        L = ctx.build(rp, col, g.n_vertices, s, dual)
+        st = ctx.stats()
+        _, ost = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual,
+                              threads=8, keep=False)
+        assert st["wedges"] == ost.wedges
+        assert st["n_pairs"] == ost.n_pairs == len(L)
+        assert digest_torch(L.a, L.b, L.w) == ost.digest
