@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark of the s-line-graph build on one MI355X.
+
+Default workload: the power-law hypergraph with 1,000,000 hyperedges over
+2,000,000 vertices (sizes truncated Zipf 2.2 on [2, 1e4], vertex popularity
+truncated Zipf 1.8 on [1, 1e5], seed 21), int32 CSR resident in HBM.  One step
+builds L_s(H) for every s in {1, 2, 4, 8, 16} with one plain sline_build call
+each (outputs stay on the device; they are freed before the next call).
+
+Printed: one JSON line with incidence entries/s over the whole step, the
+roofline of the counting stage (algorithmic bytes 12*nnz_s + 4*W_s + 12*|L_s|
+per build over the time of its counting kernels, HIP events on the library's
+stream) and the CPU oracle timed on a bounded sample of the same workload.
+
+Other forms (--form): ``dual`` (the same graph's dual, s in {2, 8, 32}).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--form", default="plain", choices=["plain", "dual"])
+    p.add_argument("--s", default=None, help="comma-separated s values")
+    p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-rows", type=int, default=0, help="rows in the CPU sample (0 = auto)")
+    return p.parse_args()
+
+
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
+
+
+def cpu_baseline(g, s_list, dual, rows_hint):
+    """The O1 oracle (all pairs, sorted merge) on a seeded sample of items.
+
+    Rows a are drawn uniformly; the oracle compares each with every b > a,
+    so the sampled time scaled by N / rows estimates the full build."""
+    import oracle
+
+    N = g.n_vertices if dual else g.n_edges
+    threads = os.cpu_count() or 1
+    rng = np.random.default_rng(12345)
+    nrows = rows_hint or max(threads * 8, 64)
+    rows = np.sort(rng.choice(N, size=min(nrows, N), replace=False)).astype(np.int32)
+    est = 0.0
+    spent = 0.0
+    for s in s_list:
+        t0 = time.perf_counter()
+        oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, rows=rows,
+                     threads=threads, keep=False)
+        dt = time.perf_counter() - t0
+        spent += dt
+        est += dt * N / len(rows)
+    value = len(s_list) * g.nnz / est
+    return {"value": value, "unit": "incidence entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"O1 naive all-pairs oracle on {len(rows)} uniformly drawn items of {N} "
+                      f"(every b > a compared), s in {list(s_list)}; {spent:.1f} s measured, "
+                      f"scaled by N/rows to {est:.0f} s for the full sweep"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rows of the result shard across GPUs without exchange; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2010_11448_amd import gen, sline
+
+    dev = torch.device("cuda", 0)
+    dual = 1 if args.form == "dual" else 0
+    s_list = tuple(int(x) for x in args.s.split(",")) if args.s else (
+        gen.DUAL_S if dual else gen.POWERLAW_S)
+    print(f"bench: generating workload (scale {args.scale})", file=sys.stderr, flush=True)
+    g = gen.powerlaw_1m(scale=args.scale)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    ctx = sline.Context(0)
+    flags = sline.SLINE_PROFILE
+    per_s = {s: [] for s in s_list}
+
+    def step(record):
+        for s in s_list:
+            t0 = time.perf_counter()
+            L = ctx.build(rp, col, g.n_vertices, s, dual, flags)
+            t1 = time.perf_counter()
+            if record:
+                per_s[s].append((t1 - t0, ctx.stats()))
+            del L
+
+    for i in range(args.warmup):
+        step(False)
+        print(f"bench: warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        print(f"bench: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / max(args.steps, 1)
+    value = len(s_list) * g.nnz / (ms_per_step / 1000.0)
+
+    alg_bytes = 0.0
+    count_ms = 0.0
+    launches = 0
+    builds = {}
+    for s in s_list:
+        recs = per_s[s]
+        times = [r[0] * 1000.0 for r in recs]
+        st = recs[0][1]
+        b = 12.0 * st["nnz_kept"] + 4.0 * st["wedges"] + 12.0 * st["n_pairs"]
+        for _, sr in recs:
+            alg_bytes += b
+            count_ms += sr["ms_count"] + sr["ms_fill"]
+            launches += 1
+        builds[str(s)] = {
+            "p50_ms": pct(times, 50), "p99_ms": pct(times, 99),
+            "pairs": st["n_pairs"], "wedges": st["wedges"], "kept_items": st["n_kept"],
+            "alg_bytes": b,
+            "ms_transpose": float(np.median([r[1]["ms_transpose"] for r in recs])),
+            "ms_prepare": float(np.median([r[1]["ms_prepare"] for r in recs])),
+            "ms_count": float(np.median([r[1]["ms_count"] for r in recs])),
+            "ms_scan": float(np.median([r[1]["ms_scan"] for r in recs])),
+            "ms_fill": float(np.median([r[1]["ms_fill"] for r in recs])),
+            "heavy_items": st["n_heavy"], "small_items": st["n_small"], "passes": st["passes"],
+        }
+    achieved = alg_bytes / 1e9 / (count_ms / 1000.0) if count_ms > 0 else 0.0
+    line = {
+        "metric": "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99",
+        "value": value,
+        "unit": "incidence entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": g.meta.get("workload", "powerlaw") + (" dual" if dual else ""),
+                   "n_edges": g.n_edges, "n_vertices": g.n_vertices, "nnz": g.nnz,
+                   "s": list(s_list), "dual": dual, "builds_per_step": len(s_list)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "counting stage (k_count_small + k_count_heavy, count and fill passes)",
+                     "alg_bytes_per_build": "12*nnz_s + 4*W_s + 12*|L_s|",
+                     "launch_pairs": launches},
+        "builds": builds,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(g, s_list, dual, args.cpu_rows)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

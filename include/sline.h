@@ -39,7 +39,10 @@ enum {
 
 /* Build flags. */
 enum {
-    SLINE_SKIP_VALIDATE = 1u /* trust the CSR: skip the well-formedness check */
+    SLINE_SKIP_VALIDATE = 1u, /* skip the strictly-increasing row check (range
+                                 checks that guard memory always run)       */
+    SLINE_PROFILE = 2u        /* time the stages with HIP events on the
+                                 context's stream (see sline_stats)          */
 };
 
 typedef struct sline_ctx sline_ctx;
@@ -100,6 +103,12 @@ typedef struct {
     int64_t n_small;      /* items counted by the one-wave kernel                 */
     int64_t n_heavy;      /* items counted by the workgroup (multi-pass) kernel   */
     int64_t passes;       /* table passes made by the workgroup kernel            */
+    /* stage times in milliseconds, filled when the build had SLINE_PROFILE  */
+    double ms_transpose;  /* row checks + transpose (scatter and row sort)        */
+    double ms_prepare;    /* s filter, per-item wedge counts, buckets             */
+    double ms_count;      /* count pass (counting kernels, pairs per item)        */
+    double ms_scan;       /* exclusive scan of pairs per item                     */
+    double ms_fill;       /* fill pass (counting kernels writing the pairs)       */
 } sline_stats;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`

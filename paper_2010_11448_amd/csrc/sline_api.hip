@@ -35,6 +35,8 @@ struct sline_ctx {
     Tuning tune;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    void *ws2 = nullptr;  // task arrays
+    size_t ws2_bytes = 0;
     int64_t *host = nullptr;  // pinned read-back area (64 int64)
 
     // counting work kept after SLINE_ECAPACITY for an immediate retry
@@ -48,6 +50,9 @@ struct sline_ctx {
     // device views into the workspace kept for the fill pass
     CountArgs fill_args{};
     int64_t fill_total = 0;
+    // stage events (SLINE_PROFILE)
+    hipEvent_t ev[8] = {};
+    bool profile = false;
 };
 
 namespace {
@@ -122,21 +127,36 @@ void ensure_ws(sline_ctx *c, size_t bytes) {
 
 void sync(sline_ctx *c, const char *where) { hip_check(c, hipStreamSynchronize(c->stream), where); }
 
+// Stage marks: 0 start, 1 after transpose, 2 after prepare, 3 after count,
+// 4 after scan, 5 before fill, 6 after fill.
+void mark(sline_ctx *c, int i) {
+    if (c->profile) hip_check(c, hipEventRecord(c->ev[i], c->stream), "event record");
+}
+
+double span_ms(sline_ctx *c, int i, int j) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[i], c->ev[j]) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0;
+    }
+    return ms;
+}
+
 struct Layout {
-    int32_t *err, *bins, *seg, *queue;
+    int32_t *err, *seg, *queue, *tcounts;
     int64_t *totals, *passes;
     int32_t *rowid, *degT, *ptrT, *fillT, *colT, *mid_list, *big_list;
     int32_t *ptrS, *cntS, *itmS;
-    int64_t *cost, *rowoff, *part64;
-    int32_t *part32, *small_list, *heavy_list, *rowcnt, *cur, *nxt;
+    int64_t *cost, *tbase, *part64;
+    int32_t *part32, *ntask, *start;
 };
 
 Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64_t M, bool filt) {
     Layout L{};
     L.err = A.take<int32_t>(4);
-    L.bins = A.take<int32_t>(130);
     L.seg = A.take<int32_t>(4);
     L.queue = A.take<int32_t>(4);
+    L.tcounts = A.take<int32_t>(4);
     L.totals = A.take<int64_t>(4);
     L.passes = A.take<int64_t>(2);
     L.rowid = A.take<int32_t>(nnz);
@@ -155,13 +175,45 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
         L.itmS = A.take<int32_t>(nnz);
     }
     L.cost = A.take<int64_t>(N);
-    L.small_list = A.take<int32_t>(N);
-    L.heavy_list = A.take<int32_t>(N);
-    L.rowcnt = A.take<int32_t>(N);
-    L.rowoff = A.take<int64_t>(N + 1);
-    L.cur = A.take<int32_t>(nnz);
-    L.nxt = A.take<int32_t>(nnz);
+    L.ntask = A.take<int32_t>(N);
+    L.tbase = A.take<int64_t>(N + 1);
+    L.start = A.take<int32_t>(nnz);
     return L;
+}
+
+// Task arrays, sized once the task count is known.
+struct TaskLayout {
+    int32_t *item, *part, *small, *big, *cnt;
+    int64_t *off, *part64;
+};
+
+TaskLayout plan_tasks(Arena &A, int64_t T) {
+    TaskLayout L{};
+    L.item = A.take<int32_t>(T);
+    L.part = A.take<int32_t>(T);
+    L.small = A.take<int32_t>(T);
+    L.big = A.take<int32_t>(T);
+    L.cnt = A.take<int32_t>(T);
+    L.off = A.take<int64_t>(T + 1);
+    L.part64 = A.take<int64_t>(scan_partials(T + 1));
+    return L;
+}
+
+void ensure_ws2(sline_ctx *c, size_t bytes) {
+    if (c->ws2_bytes >= bytes) return;
+    if (c->ws2) {
+        hip_check(c, hipStreamSynchronize(c->stream), "workspace release");
+        dev_free(c, c->ws2, c->ws2_bytes);
+        c->ws2 = nullptr;
+        c->ws2_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    c->ws2 = dev_alloc(c, want);
+    if (!c->ws2) {
+        set_err(c, "task workspace allocation of %s bytes failed", std::to_string(want).c_str());
+        throw Fail{SLINE_ENOMEM};
+    }
+    c->ws2_bytes = want;
 }
 
 void transpose(sline_ctx *c, const Layout &L, const int32_t *col, int32_t n, int64_t nnz) {
@@ -260,8 +312,11 @@ void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
         F.out_b = b;
         F.out_w = w;
         try {
+            mark(c, 5);
             hip_check(c, launch_count(c->stream, F), "fill pass");
+            mark(c, 6);
             sync(c, "fill pass");
+            if (c->profile) c->stats.ms_fill = span_ms(c, 5, 6);
         } catch (...) {
             if (owned) {
                 const size_t bytes = sizeof(int32_t) * (size_t)total;
@@ -303,11 +358,11 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         }
         c->pending.valid = false;
         run_fill(c, out, total);
-        c->stats.n_pairs = total;
         return SLINE_OK;
     }
     c->pending.valid = false;
 
+    c->profile = (flags & SLINE_PROFILE) != 0;
     const int64_t m = H.n_edges, n = H.n_vertices;
     if (m > 0 && !H.row_ptr) {
         set_err(c, "row_ptr is NULL");
@@ -367,12 +422,12 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const Layout L = plan_layout(A, m, n, nnz, N, M, filt);
 
     hip_check(c, launch_fill_i32(st, L.err, 4, 0), "zero flags");
-    hip_check(c, launch_fill_i32(st, L.bins, 130, 0), "zero bins");
     hip_check(c, launch_fill_i32(st, L.seg, 4, 0), "zero classes");
+    hip_check(c, launch_fill_i32(st, L.tcounts, 4, 0), "zero task counts");
     hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
     hip_check(c, launch_fill_i64(st, L.passes, 2, 0), "zero passes");
-    hip_check(c, launch_fill_i32(st, L.rowcnt, N, 0), "zero counts");
 
+    mark(c, 0);
     // 2. row ids and member checks (range checks always: they guard every later index)
     hip_check(c, launch_rows(st, H.row_ptr, H.col_idx, (int32_t)m, (int32_t)n, nnz,
                              (flags & SLINE_SKIP_VALIDATE) ? 0 : 1, L.rowid, L.err),
@@ -385,6 +440,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         set_err(c, "col_idx: members must lie in [0, n_vertices) and increase strictly within a row");
         return SLINE_EINVAL;
     }
+    mark(c, 1);
     // 4. roles
     const int32_t *ptrI = dual ? L.ptrT : H.row_ptr;
     const int32_t *memI = dual ? L.colT : H.col_idx;
@@ -401,11 +457,33 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         ptrS = L.ptrS;
         itmS = L.itmS;
     }
-    // 6. wedge counts and buckets
-    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, ptrS, itmS, L.cost, L.totals), "cost");
-    hip_check(c, launch_classify(st, L.cost, (int32_t)N, c->tune.small_max_wedges, L.small_list,
-                                 L.heavy_list, L.bins),
-              "buckets");
+    // 6. wedge counts, tasks
+    const Tuning tu = c->tune;
+    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, ptrS, itmS, L.cost, L.start, L.totals), "cost");
+    hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, L.ntask), "task count");
+    hip_check(c, launch_scan_i32_to_i64(st, L.ntask, N, L.tbase, L.part64), "task scan");
+    int64_t *h = c->host;
+    hip_check(c, hipMemcpyAsync(h + 0, L.tbase + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read tasks");
+    hip_check(c, hipMemcpyAsync(h + 1, L.totals, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st), "read totals");
+    sync(c, "task plan");
+    const int64_t T = h[0];
+    S.n_kept = h[1];
+    S.nnz_kept = h[2];
+    S.wedges = h[3];
+    if (T >= INT32_MAX) {
+        set_err(c, "too many counting tasks (%s)", std::to_string(T).c_str());
+        throw Fail{SLINE_ENOMEM};
+    }
+    Arena tsz;
+    plan_tasks(tsz, T);
+    ensure_ws2(c, tsz.off + 4096);
+    Arena TA;
+    TA.base = reinterpret_cast<char *>(c->ws2);
+    const TaskLayout TL = plan_tasks(TA, T);
+    hip_check(c, launch_task_fill(st, L.cost, (int32_t)N, tu, L.tbase, TL.item, TL.part, TL.small,
+                                  TL.big, L.tcounts),
+              "task fill");
+    mark(c, 2);
     // 7. count pass
     CountArgs C{};
     C.ptrI = ptrI;
@@ -415,42 +493,46 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.N = (int32_t)N;
     C.s = s;
     C.cost = L.cost;
-    C.small_list = L.small_list;
-    C.heavy_list = L.heavy_list;
-    C.bins = L.bins;
+    C.start = L.start;
+    C.task_item = TL.item;
+    C.task_part = TL.part;
+    C.small_tasks = TL.small;
+    C.big_tasks = TL.big;
+    C.task_counts = L.tcounts;
     C.queue = L.queue;
-    C.cur = L.cur;
-    C.nxt = L.nxt;
-    C.rowcnt = L.rowcnt;
-    C.rowoff = nullptr;
+    C.task_cnt = TL.cnt;
+    C.task_off = nullptr;
     C.passes = L.passes;
     C.err = L.err;
-    C.tune = c->tune;
+    C.tune = tu;
     C.n_cu = c->n_cu;
     hip_check(c, launch_count(st, C), "count pass");
-    hip_check(c, launch_scan_i32_to_i64(st, L.rowcnt, N, L.rowoff, L.part64), "pair scan");
-    int64_t *h = c->host;
-    hip_check(c, hipMemcpyAsync(h + 0, L.rowoff + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read total");
-    hip_check(c, hipMemcpyAsync(h + 1, L.totals, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st), "read totals");
+    mark(c, 3);
+    hip_check(c, launch_scan_i32_to_i64(st, TL.cnt, T, TL.off, TL.part64), "pair scan");
+    mark(c, 4);
+    hip_check(c, hipMemcpyAsync(h + 0, TL.off + T, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read total");
     hip_check(c, hipMemcpyAsync(h + 4, L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read passes");
-    hip_check(c, hipMemcpyAsync(h + 5, L.bins + 128, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read bins");
+    hip_check(c, hipMemcpyAsync(h + 5, L.tcounts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read task counts");
     hip_check(c, hipMemcpyAsync(h + 6, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
     sync(c, "count pass");
     const int64_t total = h[0];
     const int32_t *hb = reinterpret_cast<const int32_t *>(h + 5);
-    S.n_kept = h[1];
-    S.nnz_kept = h[2];
-    S.wedges = h[3];
     S.passes = h[4];
     S.n_small = hb[0];
     S.n_heavy = hb[1];
     S.n_pairs = total;
+    if (c->profile) {
+        S.ms_transpose = span_ms(c, 0, 1);
+        S.ms_prepare = span_ms(c, 1, 2);
+        S.ms_count = span_ms(c, 2, 3);
+        S.ms_scan = span_ms(c, 3, 4);
+    }
     if (reinterpret_cast<const int32_t *>(h + 6)[0] & kErrInternal) {
         set_err(c, "internal error: counting table overflow");
         return SLINE_EDEVICE;
     }
     c->stats = S;
-    C.rowoff = L.rowoff;
+    C.task_off = TL.off;
     C.passes = nullptr;
     c->fill_args = C;
     c->fill_total = total;
@@ -499,18 +581,26 @@ sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const s
         delete c;
         return SLINE_EDEVICE;
     }
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            sline_destroy(c);
+            return SLINE_EDEVICE;
+        }
+    }
     *ctx = c;
     return SLINE_OK;
 }
 
 void sline_destroy(sline_ctx *c) {
     if (!c) return;
-    if (c->ws) {
-        (void)hipStreamSynchronize(c->stream);
-        dev_free(c, c->ws, c->ws_bytes);
-        (void)hipStreamSynchronize(c->stream);
-    }
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ws) dev_free(c, c->ws, c->ws_bytes);
+    if (c->ws2) dev_free(c, c->ws2, c->ws2_bytes);
+    (void)hipStreamSynchronize(c->stream);
     if (c->host) (void)hipHostFree(c->host);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

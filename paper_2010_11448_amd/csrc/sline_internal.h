@@ -22,10 +22,11 @@ enum : int32_t {
 // Tunable launch parameters of the counting kernels (the autotuner sets them).
 struct Tuning {
     int32_t small_max_wedges = 512;  // items with W_a up to this go to the one-wave kernel
+    int32_t task_wedges = 3600;      // wedges per workgroup task (j sub-range of an item)
+    int32_t group_parts = 8;         // consecutive tasks of one item run by one workgroup
     int32_t light_len = 8;           // member runs up to this are walked by one lane
     int32_t small_grid_per_cu = 16;  // one-wave workgroups per CU for the small kernel
-    int32_t heavy_grid_per_cu = 4;   // resident workgroups per CU for the heavy kernel
-    int32_t heavy_load_pct = 45;     // target table load of a heavy pass, percent
+    int32_t task_grid_per_cu = 4;    // resident workgroups per CU for the task kernel
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -37,10 +38,10 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kSegSortLds = 16384;
 constexpr int kSegSortSmall = 32;
 
-// Table sizes (slots) of the counting kernels.
+// Table sizes (home slots) of the counting kernels.
 constexpr int kSmallSlots = 1024;
-constexpr int kHeavySlots = 4096;
-constexpr int kHeavyThreads = 256;
+constexpr int kTaskSlots = 8960;  // + 64 pad: 9024 packed 4-byte slots, four workgroups per CU
+constexpr int kTaskThreads = 256;
 
 // ------------------------------------------------------------ launchers
 // Every launcher enqueues on `st` and returns the launch status.
@@ -82,28 +83,37 @@ hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itm
                          const int32_t *ptrI, int32_t s, const int32_t *ptrS, int32_t *cntS,
                          int32_t *itmS);
 
-// Per-item exact wedge count W_a and the run totals.
+// Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
+// in N_s(v) for member incidence k of a kept item a) and the run totals:
 // totals[0] = kept items, [1] = kept incidences, [2] = wedges.
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
-                       int64_t *totals);
+                       int32_t *start, int64_t *totals);
 
-// Buckets: small list (one-wave kernel) and heavy list ordered by descending
-// log2(W_a).  `bins` holds 64 counters + 64 cursors + 2 totals (int32).
-hipError_t launch_classify(hipStream_t st, const int64_t *cost, int32_t N, int32_t small_max,
-                           int32_t *small_list, int32_t *heavy_list, int32_t *bins);
+// Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
+// candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is
+// listed in small_tasks (W_a <= small_max) or big_tasks; counts[0] / [1]
+// receive the list lengths.
+hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                             int32_t *ntask);
+// big_tasks receives, per group of up to group_parts consecutive tasks of an
+// item, the index of the group's first task; counts[1] = number of groups.
+hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                            const int64_t *tbase, int32_t *task_item, int32_t *task_part,
+                            int32_t *small_tasks, int32_t *big_tasks, int32_t *counts);
 
 struct CountArgs {
     const int32_t *ptrI, *memI;  // item lists
     const int32_t *ptrS, *itmS;  // filtered membership lists
     int32_t N, s;
-    const int64_t *cost;
-    const int32_t *small_list, *heavy_list;
-    const int32_t *bins;         // n_small at bins[128], n_heavy at bins[129]
-    int32_t *queue;              // heavy work-queue head (reset by the launcher)
-    int32_t *cur, *nxt;          // per item-incidence cursors (heavy kernel)
-    int32_t *rowcnt;             // count mode: pairs per item
-    const int64_t *rowoff;       // fill mode: output offset per item (nullptr = count mode)
+    const int64_t *cost;         // W_a per item
+    const int32_t *start;        // back-pointers per item incidence (see launch_cost)
+    const int32_t *task_item, *task_part;
+    const int32_t *small_tasks, *big_tasks;
+    const int32_t *task_counts;  // [0] small tasks, [1] task groups
+    int32_t *queue;              // big-task queue head (reset by the launcher)
+    int32_t *task_cnt;           // count mode: pairs per task
+    const int64_t *task_off;     // fill mode: output offset per task (nullptr = count mode)
     int32_t *out_a, *out_b, *out_w;
     int64_t *passes;
     int32_t *err;

@@ -334,11 +334,13 @@ __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32
 }
 
 // One wave per item (grid-stride): W_a = sum over members v of the number of
-// kept items b > a in N_s(v); 0 for items with |S_a| < s.
+// kept items b > a in N_s(v); 0 for items with |S_a| < s.  For every member
+// incidence k of a kept item, start[k] = index in itmS of the first item > a
+// in N_s(v) (the back-pointer where a's walk over v begins).
 __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t *memI,
                                               int32_t N, int32_t s, const int32_t *ptrS,
                                               const int32_t *itmS, int64_t *cost,
-                                              int64_t *totals) {
+                                              int32_t *start, int64_t *totals) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -353,7 +355,9 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
         for (int32_t k = b + lane; k < e; k += kWave) {
             const int32_t v = memI[k];
             const int32_t lo = ptrS[v], hi = ptrS[v + 1];
-            c += hi - upper_bound(itmS, lo, hi, (int32_t)a);
+            const int32_t st = upper_bound(itmS, lo, hi, (int32_t)a);
+            start[k] = st;
+            c += hi - st;
         }
         c = wave_sum(c);
         if (lane == 0) cost[a] = c;
@@ -365,51 +369,6 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
         atomicAdd((unsigned long long *)&totals[0], (unsigned long long)kept);
         atomicAdd((unsigned long long *)&totals[1], (unsigned long long)kept_nnz);
         atomicAdd((unsigned long long *)&totals[2], (unsigned long long)wedges);
-    }
-}
-
-// --------------------------------------------------------- buckets
-// bins[0..63]: heavy items per log2 bin; bins[64..127]: bin cursors;
-// bins[128]: small count; bins[129]: heavy count.
-
-__device__ __forceinline__ int log2_bin(int64_t c) { return 63 - __clzll((unsigned long long)c); }
-
-__global__ void k_classify_count(const int64_t *cost, int32_t N, int32_t small_max,
-                                 int32_t *small_list, int32_t *bins) {
-    __shared__ int32_t hist[64];
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
-    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = cost[a];
-        if (c <= 0) continue;
-        if (c <= small_max) small_list[atomicAdd(&bins[128], 1)] = (int32_t)a;
-        else atomicAdd(&hist[log2_bin(c)], 1);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 64; i += blockDim.x)
-        if (hist[i]) atomicAdd(&bins[i], hist[i]);
-}
-
-// Cursors: bins processed from the most expensive (longest first).
-__global__ void k_classify_offsets(int32_t *bins) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int32_t run = 0;
-        for (int b = 63; b >= 0; --b) {
-            bins[64 + b] = run;
-            run += bins[b];
-        }
-        bins[129] = run;
-    }
-}
-
-__global__ void k_classify_scatter(const int64_t *cost, int32_t N, int32_t small_max,
-                                   int32_t *heavy_list, int32_t *bins) {
-    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = cost[a];
-        if (c <= small_max) continue;
-        heavy_list[atomicAdd(&bins[64 + log2_bin(c)], 1)] = (int32_t)a;
     }
 }
 
@@ -536,20 +495,10 @@ hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itm
 
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
-                       int64_t *totals) {
+                       int32_t *start, int64_t *totals) {
     if (N <= 0) return hipSuccess;
     k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s, ptrS,
-                                                                     itmS, cost, totals);
-    return hipGetLastError();
-}
-
-hipError_t launch_classify(hipStream_t st, const int64_t *cost, int32_t N, int32_t small_max,
-                           int32_t *small_list, int32_t *heavy_list, int32_t *bins) {
-    if (N <= 0) return hipSuccess;
-    const int g = grid_for(N, 256, 4096);
-    k_classify_count<<<g, 256, 0, st>>>(cost, N, small_max, small_list, bins);
-    k_classify_offsets<<<1, 64, 0, st>>>(bins);
-    k_classify_scatter<<<g, 256, 0, st>>>(cost, N, small_max, heavy_list, bins);
+                                                                     itmS, cost, start, totals);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ SLINE_ECAPACITY = -3
 SLINE_EDEVICE = -4
 SLINE_EBUSY = -5
 SLINE_SKIP_VALIDATE = 1
+SLINE_PROFILE = 2
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -42,10 +43,12 @@ class sline_edges(ctypes.Structure):
 class sline_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("n_items", "nnz", "nnz_kept", "n_kept", "wedges", "n_pairs", "n_small",
-                 "n_heavy", "passes")]
+                 "n_heavy", "passes")] + [(k, ctypes.c_double) for k in
+                ("ms_transpose", "ms_prepare", "ms_count", "ms_scan", "ms_fill")]
 
     def as_dict(self) -> dict:
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
+                for k, _ in self._fields_}
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -184,3 +184,22 @@ def test_stats_match_oracle(ctx, dev):
         assert st["wedges"] == ost.wedges
         assert st["n_pairs"] == ost.n_pairs == len(L)
         assert digest_torch(L.a, L.b, L.w) == ost.digest
+
+
+def test_wide_items_and_long_member_lists(ctx, dev):
+    """Items with tens of thousands of members: packed counters need more
+    count bits (narrower key ranges, forced range splits) and members beyond
+    the per-thread cursor window; checked against the wedge oracle."""
+    st = gen.Stream(77)
+    m, n = 300_000, 400_000
+    sets = [sorted(set(st.integers(0, n - 1, 2).tolist())) for _ in range(m)]
+    for pos in (5, 150_000, 299_990):
+        sets[pos] = sorted(set(st.integers(0, n - 1, 30_000).tolist()))
+    sets[7] = sets[5][:20_000]
+    g = gen.from_sets(sets, n)
+    rp, col = to_device(g, dev)
+    for dual, s in ((0, 1), (0, 2), (0, 3), (1, 3), (1, 4)):
+        print(f"case: wide items s={s} dual={dual}", flush=True)
+        L = ctx.build(rp, col, g.n_vertices, s, dual)
+        ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, threads=8)
+        assert_same(L, ref, f"wide s={s} dual={dual}")
