@@ -111,6 +111,31 @@ typedef struct {
     double ms_fill;       /* fill pass (counting kernels writing the pairs)       */
 } sline_stats;
 
+/* Launch parameters of the counting stage (they change speed, never the
+ * result).  Defaults suit MI355X; sline_set_tuning rejects values outside the
+ * stated ranges with SLINE_EINVAL.
+ *   small_max_wedges   items with at most this many wedges are counted by one
+ *                      wave each (0..512)
+ *   task_wedges        wedges per workgroup task, the unit an item's candidate
+ *                      range is cut into (64..1048576)
+ *   group_parts        consecutive tasks of one item run by one workgroup (1..1024)
+ *   light_len          member runs expected shorter than this are walked by a
+ *                      single lane (0..64)
+ *   small_grid_per_cu  resident one-wave workgroups per CU (1..64)
+ *   task_grid_per_cu   resident task workgroups per CU (1..16)
+ *   stage_max_bytes    cap of the staging pool that lets one counting pass
+ *                      produce the result; tasks that do not fit are counted
+ *                      again (>= 0; 0 = always two passes) */
+typedef struct {
+    int32_t small_max_wedges;
+    int32_t task_wedges;
+    int32_t group_parts;
+    int32_t light_len;
+    int32_t small_grid_per_cu;
+    int32_t task_grid_per_cu;
+    int64_t stage_max_bytes;
+} sline_tuning;
+
 /* Create a context on HIP device `device` issuing work on `hip_stream`
  * (a hipStream_t; NULL = the default stream).  `alloc` may be NULL; it is
  * copied.  Returns SLINE_EDEVICE if the device cannot be used. */
@@ -135,6 +160,10 @@ sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
 /* Release the arrays of a library-allocated result and zero the struct.
  * Caller-owned buffers (capacity > 0) are not touched. */
 sline_status sline_edges_free(sline_ctx *ctx, sline_edges *edges);
+
+/* Read / replace the context's launch parameters (host structs). */
+sline_status sline_get_tuning(sline_ctx *ctx, sline_tuning *tuning);
+sline_status sline_set_tuning(sline_ctx *ctx, const sline_tuning *tuning);
 
 /* Statistics of the last successful build on `ctx`. */
 sline_status sline_last_stats(sline_ctx *ctx, sline_stats *stats);

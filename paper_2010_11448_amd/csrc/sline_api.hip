@@ -50,6 +50,10 @@ struct sline_ctx {
     // device views into the workspace kept for the fill pass
     CountArgs fill_args{};
     int64_t fill_total = 0;
+    int32_t fill_records = 0;   // staged ranges to copy (stage mode)
+    int32_t fill_need = 0;      // tasks to recompute (-1: all, count mode)
+    void *pool = nullptr;       // staging pool of the last build
+    size_t pool_bytes = 0;
     // stage events (SLINE_PROFILE)
     hipEvent_t ev[8] = {};
     bool profile = false;
@@ -127,6 +131,39 @@ void ensure_ws(sline_ctx *c, size_t bytes) {
 
 void sync(sline_ctx *c, const char *where) { hip_check(c, hipStreamSynchronize(c->stream), where); }
 
+void release_pool(sline_ctx *c) {
+    if (!c->pool) return;
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->pool, c->pool_bytes);
+    c->pool = nullptr;
+    c->pool_bytes = 0;
+}
+
+// Staging pool for `want` pairs (8 bytes each), halving on failure; returns
+// the pairs it holds (0: none, count the pairs in a separate pass instead).
+int64_t acquire_pool(sline_ctx *c, int64_t want) {
+    release_pool(c);
+    int64_t cap = std::min<int64_t>(want, c->tune.stage_max_bytes / 8);
+    while (cap >= (1 << 20)) {
+        void *p = dev_alloc(c, (size_t)cap * 8);
+        if (p) {
+            c->pool = p;
+            c->pool_bytes = (size_t)cap * 8;
+            return cap;
+        }
+        cap /= 2;
+    }
+    if (cap > 0) {
+        void *p = dev_alloc(c, (size_t)cap * 8);
+        if (p) {
+            c->pool = p;
+            c->pool_bytes = (size_t)cap * 8;
+            return cap;
+        }
+    }
+    return 0;
+}
+
 // Stage marks: 0 start, 1 after transpose, 2 after prepare, 3 after count,
 // 4 after scan, 5 before fill, 6 after fill.
 void mark(sline_ctx *c, int i) {
@@ -183,12 +220,20 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
 
 // Task arrays, sized once the task count is known.
 struct TaskLayout {
-    int32_t *item, *part, *small, *big, *cnt;
+    int32_t *item, *part, *small, *big, *cnt, *need, *ctrs;
     int64_t *off, *part64;
+    unsigned long long *pool_head;
+    StageRec *log;
+    int32_t log_cap;
 };
 
 TaskLayout plan_tasks(Arena &A, int64_t T) {
     TaskLayout L{};
+    L.log_cap = (int32_t)std::min<int64_t>(INT32_MAX - 1, 2 * T + 65536);
+    L.pool_head = A.take<unsigned long long>(1);
+    L.ctrs = A.take<int32_t>(4);  // [0] log head, [1] tasks flagged
+    L.log = A.take<StageRec>(L.log_cap);
+    L.need = A.take<int32_t>(T);
     L.item = A.take<int32_t>(T);
     L.part = A.take<int32_t>(T);
     L.small = A.take<int32_t>(T);
@@ -313,9 +358,27 @@ void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
         F.out_w = w;
         try {
             mark(c, 5);
-            hip_check(c, launch_count(c->stream, F), "fill pass");
+            if (c->fill_need >= 0) {
+                // stage mode: move the staged ranges, recompute tasks that found no room
+                hip_check(c, launch_stage_copy(c->stream, F, c->fill_records), "stage copy");
+                if (c->fill_need > 0) {
+                    F.mode = kModeFill;
+                    hip_check(c, launch_count(c->stream, F), "fill pass (recompute)");
+                }
+            } else {
+                F.mode = kModeFill;
+                F.need = nullptr;
+                hip_check(c, launch_count(c->stream, F), "fill pass");
+            }
             mark(c, 6);
+            hip_check(c, hipMemcpyAsync(c->host + 8, F.err, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                        c->stream),
+                      "read flags");
             sync(c, "fill pass");
+            if (reinterpret_cast<const int32_t *>(c->host + 8)[0] & kErrInternal) {
+                set_err(c, "internal error: inconsistent staged ranges");
+                throw Fail{SLINE_EDEVICE};
+            }
             if (c->profile) c->stats.ms_fill = span_ms(c, 5, 6);
         } catch (...) {
             if (owned) {
@@ -358,9 +421,11 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         }
         c->pending.valid = false;
         run_fill(c, out, total);
+        release_pool(c);
         return SLINE_OK;
     }
     c->pending.valid = false;
+    release_pool(c);
 
     c->profile = (flags & SLINE_PROFILE) != 0;
     const int64_t m = H.n_edges, n = H.n_vertices;
@@ -484,8 +549,18 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
                                   TL.big, L.tcounts),
               "task fill");
     mark(c, 2);
-    // 7. count pass
+    // 7. one counting pass: pairs per task, each range's pairs staged in a pool
+    const int64_t want_pool = S.wedges / s;  // every pair of L_s accounts for >= s wedges
+    const int64_t pool_cap = want_pool > 0 ? acquire_pool(c, want_pool) : 0;
+    hip_check(c, launch_fill_i32(st, TL.need, T, 0), "zero flags");
+    // unused records of a reserved log chunk must read as empty
+    hip_check(c, launch_fill_i32(st, reinterpret_cast<int32_t *>(TL.log),
+                                 (int64_t)TL.log_cap * (int64_t)(sizeof(StageRec) / 4), 0),
+              "zero log");
+    hip_check(c, launch_fill_i32(st, TL.ctrs, 4, 0), "zero counters");
+    hip_check(c, launch_fill_i64(st, reinterpret_cast<int64_t *>(TL.pool_head), 1, 0), "zero pool head");
     CountArgs C{};
+    C.mode = pool_cap > 0 ? kModeStage : kModeCount;
     C.ptrI = ptrI;
     C.memI = memI;
     C.ptrS = ptrS;
@@ -496,12 +571,29 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.start = L.start;
     C.task_item = TL.item;
     C.task_part = TL.part;
+    C.n_tasks = (int32_t)T;
     C.small_tasks = TL.small;
     C.big_tasks = TL.big;
     C.task_counts = L.tcounts;
     C.queue = L.queue;
     C.task_cnt = TL.cnt;
     C.task_off = nullptr;
+    C.pool_b = reinterpret_cast<int32_t *>(c->pool);
+    C.pool_w = c->pool ? reinterpret_cast<int32_t *>(c->pool) + pool_cap : nullptr;
+    C.pool_cap = pool_cap;
+    C.pool_head = TL.pool_head;
+    C.log = TL.log;
+    C.log_cap = TL.log_cap;
+    {
+        // chunks small enough that every resident workgroup gets several
+        const int64_t groups = (int64_t)c->n_cu * (tu.small_grid_per_cu + tu.task_grid_per_cu);
+        C.pool_chunk = std::max<int64_t>(256, std::min<int64_t>(1 << 16, pool_cap / (8 * groups)));
+        C.log_chunk = (int32_t)std::max<int64_t>(
+            1, std::min<int64_t>(256, (int64_t)TL.log_cap / (8 * groups)));
+    }
+    C.log_head = TL.ctrs;
+    C.need = TL.need;
+    C.need_count = TL.ctrs + 1;
     C.passes = L.passes;
     C.err = L.err;
     C.tune = tu;
@@ -514,9 +606,11 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     hip_check(c, hipMemcpyAsync(h + 4, L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read passes");
     hip_check(c, hipMemcpyAsync(h + 5, L.tcounts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read task counts");
     hip_check(c, hipMemcpyAsync(h + 6, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    hip_check(c, hipMemcpyAsync(h + 7, TL.ctrs, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read stage counters");
     sync(c, "count pass");
     const int64_t total = h[0];
     const int32_t *hb = reinterpret_cast<const int32_t *>(h + 5);
+    const int32_t *hc = reinterpret_cast<const int32_t *>(h + 7);
     S.passes = h[4];
     S.n_small = hb[0];
     S.n_heavy = hb[1];
@@ -531,6 +625,8 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         set_err(c, "internal error: counting table overflow");
         return SLINE_EDEVICE;
     }
+    c->fill_records = C.mode == kModeStage ? std::min(hc[0], TL.log_cap) : 0;
+    c->fill_need = C.mode == kModeStage ? hc[1] : -1;
     c->stats = S;
     C.task_off = TL.off;
     C.passes = nullptr;
@@ -549,6 +645,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     }
     // 8. fill
     run_fill(c, out, total);
+    release_pool(c);
     return SLINE_OK;
 }
 
@@ -594,6 +691,7 @@ sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const s
 
 void sline_destroy(sline_ctx *c) {
     if (!c) return;
+    release_pool(c);
     (void)hipStreamSynchronize(c->stream);
     if (c->ws) dev_free(c, c->ws, c->ws_bytes);
     if (c->ws2) dev_free(c, c->ws2, c->ws2_bytes);
@@ -637,6 +735,39 @@ sline_status sline_edges_free(sline_ctx *c, sline_edges *e) {
         e->a = e->b = e->w = nullptr;
         e->n_pairs = 0;
     }
+    return SLINE_OK;
+}
+
+sline_status sline_get_tuning(sline_ctx *c, sline_tuning *t) {
+    if (!c || !t) return SLINE_EINVAL;
+    t->small_max_wedges = c->tune.small_max_wedges;
+    t->task_wedges = c->tune.task_wedges;
+    t->group_parts = c->tune.group_parts;
+    t->light_len = c->tune.light_len;
+    t->small_grid_per_cu = c->tune.small_grid_per_cu;
+    t->task_grid_per_cu = c->tune.task_grid_per_cu;
+    t->stage_max_bytes = c->tune.stage_max_bytes;
+    return SLINE_OK;
+}
+
+sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
+    if (!c || !t) return SLINE_EINVAL;
+    auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
+    if (!in(t->small_max_wedges, 0, kSmallSlots / 2) || !in(t->task_wedges, 64, 1 << 20) ||
+        !in(t->group_parts, 1, 1024) || !in(t->light_len, 0, 64) ||
+        !in(t->small_grid_per_cu, 1, 64) || !in(t->task_grid_per_cu, 1, 16) ||
+        t->stage_max_bytes < 0) {
+        c->last_error = "tuning value out of range";
+        return SLINE_EINVAL;
+    }
+    c->pending.valid = false;
+    c->tune.small_max_wedges = t->small_max_wedges;
+    c->tune.task_wedges = t->task_wedges;
+    c->tune.group_parts = t->group_parts;
+    c->tune.light_len = t->light_len;
+    c->tune.small_grid_per_cu = t->small_grid_per_cu;
+    c->tune.task_grid_per_cu = t->task_grid_per_cu;
+    c->tune.stage_max_bytes = t->stage_max_bytes;
     return SLINE_OK;
 }
 

@@ -26,13 +26,16 @@
 //   * hashed (hi - lo  > slots): the word packs (j - lo + 1) above the low
 //     `cb` bits, which hold the count (cb = bit length of |S_a|, so a count
 //     never reaches the key field; ranges too wide for the key field are
-//     split).  Home slot = (j - lo) * slots / (hi - lo), one v_mul_hi_u32;
-//     linear probing forward without wrap-around into `pad` extra slots.
-//     The map is monotone, so two candidates out of order in slot order sit
-//     in the same run of occupied slots (a cluster): extraction ranks each
-//     candidate against its cluster neighbours and writes it to its final
-//     position.  A probe that runs off the table marks the range, which is
-//     then cleared and split in halves (depth-first, left half first).
+//     split).  Slots form buckets of four words read with one 16-byte LDS
+//     load.  Home bucket = (j - lo) * buckets / (hi - lo), one v_mul_hi_u32;
+//     a candidate takes its home bucket or, when that is full, the next
+//     bucket with room (no wrap-around; `pad` extra slots at the end).  The
+//     map is monotone, so a bucket with a free slot separates smaller from
+//     larger candidates: candidates can only be out of order inside a run of
+//     full buckets ended by a non-full one (a cluster), and extraction ranks
+//     each candidate against its cluster to write it to its final position.
+//     A probe that runs off the table marks the range, which is then cleared
+//     and split in halves (depth-first, left half first).
 //
 // Two kernels: k_count_small (one wave per item with W_a <= small_max) and
 // k_count_tasks (one workgroup per task group).  Each runs twice: a count pass
@@ -74,8 +77,8 @@ struct Range {
     int32_t lo;      // first candidate id
     int32_t hi;      // one past the last candidate id
     uint32_t span;   // hi - lo
-    uint32_t mul;    // hashed: home = mulhi(j - lo, mul); 0 = dense
-    int32_t limit;   // slots in use (home slots + pad when hashed)
+    uint32_t mul;    // hashed: home bucket = mulhi(j - lo, mul); 0 = dense
+    int32_t limit;   // slots in use (home slots + pad when hashed; a multiple of 4)
     int32_t cb;      // hashed: count bits of a slot word
     uint32_t cmask;  // (1 << cb) - 1
 };
@@ -93,7 +96,7 @@ __device__ __forceinline__ Range make_range(int32_t lo, int32_t hi, int32_t slot
         r.mul = 0;
         r.limit = (int32_t)span;
     } else {
-        r.mul = (uint32_t)(((uint64_t)slots << 32) / (uint64_t)span);
+        r.mul = (uint32_t)(((uint64_t)(slots >> 2) << 32) / (uint64_t)span);
         r.limit = slots + pad;
     }
     return r;
@@ -102,6 +105,40 @@ __device__ __forceinline__ Range make_range(int32_t lo, int32_t hi, int32_t slot
 // A hashed range whose ids do not fit the key field of a slot word.
 __device__ __forceinline__ bool too_wide(const Range &R) {
     return R.mul != 0 && (uint64_t)R.span >= (1ull << (32 - R.cb));
+}
+
+// Hashed insertion of a wedge with key field `tag`, starting at bucket b whose
+// contents were read as q.  Returns false if the probe ran off the table.
+__device__ __forceinline__ bool tab_probe(uint32_t *tab, const Range &R, uint32_t tag, int32_t b,
+                                          uint4 q) {
+    const uint32_t hmask = ~R.cmask;
+    const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
+    const int32_t nb = R.limit >> 2;
+    for (;;) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        int32_t hit = -1, empty = -1;
+#pragma unroll
+        for (int i = 3; i >= 0; --i) {
+            if ((w[i] & hmask) == tag) hit = i;
+            if (w[i] == 0u) empty = i;
+        }
+        if (hit >= 0) {
+            atomicAdd(&tab[4 * b + hit], 1u);
+            return true;
+        }
+        if (empty >= 0) {
+            const uint32_t old = atomicCAS(&tab[4 * b + empty], 0u, tag | 1u);
+            if (old == 0u) return true;  // inserted with count 1
+            if ((old & hmask) == tag) {
+                atomicAdd(&tab[4 * b + empty], 1u);
+                return true;
+            }
+            // another candidate took the slot: look at this bucket again
+        } else if (++b >= nb) {
+            return false;  // full bucket without the key: next bucket
+        }
+        q = t4[b];
+    }
 }
 
 // Count one wedge ending at candidate j.  Returns false if the probe ran off
@@ -113,27 +150,58 @@ __device__ __forceinline__ bool tab_add(uint32_t *tab, const Range &R, int32_t j
         atomicAdd(&tab[x], 1u);
         return true;
     }
-    const uint32_t tag = (x + 1u) << R.cb;
-    for (int32_t p = (int32_t)__umulhi(x, R.mul); p < R.limit; ++p) {
-        uint32_t w = lds_load(&tab[p]);
-        if (w == 0u) {
-            w = atomicCAS(&tab[p], 0u, tag | 1u);
-            if (w == 0u) return true;  // inserted with count 1
-        }
-        if ((w & ~R.cmask) == tag) {
-            atomicAdd(&tab[p], 1u);
-            return true;
-        }
+    const int32_t b = (int32_t)__umulhi(x, R.mul);
+    return tab_probe(tab, R, (x + 1u) << R.cb, b, reinterpret_cast<const uint4 *>(tab)[b]);
+}
+
+// Count up to four wedges (a candidate >= R.hi means none); the home buckets
+// are read together before any of them is resolved.
+__device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t j0, int32_t j1,
+                                         int32_t j2, int32_t j3) {
+    const int32_t j[4] = {j0, j1, j2, j3};
+    uint32_t x[4];
+    bool in[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[i] = (uint32_t)(j[i] - R.lo);
+        in[i] = j[i] < R.hi && x[i] < R.span;
     }
-    return false;
+    if (R.mul == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (in[i]) atomicAdd(&tab[x[i]], 1u);
+        return true;
+    }
+    const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
+    int32_t b[4];
+    uint4 q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b[i] = in[i] ? (int32_t)__umulhi(x[i], R.mul) : 0;
+        if (in[i]) q[i] = t4[b[i]];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (in[i]) ok &= tab_probe(tab, R, (x[i] + 1u) << R.cb, b[i], q[i]);
+    return ok;
 }
 
 struct Smem {
-    uint32_t *tab;  // table words
-    int2 *runs;     // long member runs of the current range
-    int32_t *misc;  // [0] run count, [1] overflow, [2] stack depth, [3..] per-wave words
-    int2 *stack;    // ranges still to process
+    uint32_t *tab;       // table words
+    int2 *runs;          // long member runs of the current range
+    int32_t *taken;      // per run: entries of the run inside the current range
+    int32_t *misc;       // see kMisc*
+    int2 *stack;         // ranges still to process
+    uint64_t *pool_cur;  // [next, end) of this workgroup's pool chunk
+    int32_t *log_cur;    // [next, end) of this workgroup's log chunk
 };
+
+// misc words: short-run count, overflow flag, stack depth, staging
+// reservation (ok, offset low, offset high), long-run count, then one word
+// per wave.
+constexpr int kMiscRuns = 0, kMiscOverflow = 1, kMiscDepth = 2, kMiscStageOk = 3,
+              kMiscStageLo = 4, kMiscStageHi = 5, kMiscLong = 6, kMiscWave = 7;
 
 // One member's walk over [cur, end) of N_s(v) for the range R, one lane:
 // reads four entries at a time and stops at the first id >= R.hi.  Returns
@@ -142,17 +210,12 @@ __device__ __forceinline__ int32_t walk_lane(const int32_t *itmS, int32_t cur, i
                                              const Range &R, const Smem &S, bool &ok) {
     int32_t p = cur;
     while (p < end) {
-        int32_t j[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) j[q] = (p + q < end) ? itmS[p + q] : INT32_MAX;
-        int32_t taken = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j[q] < R.hi) {
-                ok &= tab_add(S.tab, R, j[q]);
-                ++taken;
-            }
-        }
+        const int32_t j0 = itmS[p];
+        const int32_t j1 = (p + 1 < end) ? itmS[p + 1] : INT32_MAX;
+        const int32_t j2 = (p + 2 < end) ? itmS[p + 2] : INT32_MAX;
+        const int32_t j3 = (p + 3 < end) ? itmS[p + 3] : INT32_MAX;
+        ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
+        const int32_t taken = (j0 < R.hi) + (j1 < R.hi) + (j2 < R.hi) + (j3 < R.hi);
         p += taken;
         if (taken < 4) break;
     }
@@ -179,20 +242,31 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
     for (int i = 0; i < kR; ++i) {
         slot[i] = -1;
         nc[i] = cur[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
         const int32_t k = k0 + (int32_t)threadIdx.x + i * NT;
         if (k < k1 && cur[i] < end[i]) {
             const float est = (float)(end[i] - cur[i]) * frac;
-            if (est <= light) {
-                nc[i] = walk_lane(A.itmS, cur[i], end[i], R, S, ok);
-            } else {
-                const int32_t sl = atomicAdd(&S.misc[0], 1);
-                if (sl < RUNCAP) {
-                    S.runs[sl] = make_int2(cur[i], end[i]);
-                    slot[i] = sl;
+            int32_t sl = -1;
+            if (est > light) {
+                // short runs (one 256-entry chunk expected) take the first half
+                // of the run list, long runs the second half
+                constexpr int32_t half = RUNCAP / 2;
+                if (est * 1.25f + 32.0f < (float)(4 * kWave)) {
+                    sl = atomicAdd(&S.misc[kMiscRuns], 1);
+                    sl = sl < half ? sl : -1;
                 } else {
-                    nc[i] = walk_lane(A.itmS, cur[i], end[i], R, S, ok);
+                    sl = atomicAdd(&S.misc[kMiscLong], 1);
+                    sl = sl < half ? half + sl : -1;
+                }
+                if (sl >= 0) {
+                    S.runs[sl] = make_int2(cur[i], end[i]);
+                    S.taken[sl] = 0;
                 }
             }
+            if (sl < 0) nc[i] = walk_lane(A.itmS, cur[i], end[i], R, S, ok);
+            slot[i] = sl;
         }
     }
     // members past the register window: locate the range by binary search
@@ -203,42 +277,59 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
         walk_lane(A.itmS, b, e0, R, S, ok);
     }
     __syncthreads();
-    const int32_t nrun = min(S.misc[0], RUNCAP);
-    for (int32_t h = wid; h < nrun; h += W) {
-        const int2 rr = S.runs[h];
-        int32_t p = rr.x;
+    // Runs are walked 256 entries at a time.  Short runs (one chunk expected)
+    // go to the waves in turn; a long run is cut into chunks sized by its
+    // expected length, shared by all waves.  The entries below R.hi form a
+    // prefix of the run, so the chunk counts add up to it; the wave holding
+    // the last planned chunk continues while the run goes on.  (A run that
+    // found its half of the list full was walked by its own lane.)
+    constexpr int32_t kChunk = 4 * kWave;
+    constexpr int32_t half = RUNCAP / 2;
+    const int32_t nshort = min(S.misc[kMiscRuns], half);
+    const int32_t nlong = min(S.misc[kMiscLong], half);
+    for (int32_t h = wid < nshort ? wid : nshort; h < nshort + nlong;) {
+        const bool is_long = h >= nshort;
+        const int32_t r = is_long ? half + (h - nshort) : h;
+        const int2 rr = S.runs[r];
         const int32_t e = rr.y;
-        const float est = (float)(e - p) * frac;
-        const int32_t nq = min(4, max(1, (int32_t)((est * 1.25f + 16.0f) * (1.0f / kWave)) + 1));
-        for (;;) {
-            int32_t j[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t idx = p + q * kWave + lane;
-                j[q] = (q < nq && idx < e) ? A.itmS[idx] : INT32_MAX;
-            }
-            int32_t taken = 0;
-            bool full = true;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q < nq) {
-                    const bool in = j[q] < R.hi;
-                    const uint64_t bal = __ballot(in);
-                    if (in) ok &= tab_add(S.tab, R, j[q]);
-                    taken += __popcll(bal);
-                    full &= bal == ~0ull;
-                }
-            }
-            p += taken;
-            if (!full) break;
+        int32_t nch = 1, c0 = 0, cs = 1;
+        if (is_long) {
+            const float est = (float)(e - rr.x) * frac;
+            nch = max(1, (int32_t)((est * 1.25f + 32.0f) * (1.0f / kChunk)) + 1);
+            c0 = (wid + W - (h % W)) % W;
+            cs = W;
         }
-        if (lane == 0) S.runs[h].x = p;
+        int32_t got = 0;
+        for (int32_t c = c0; c < nch; c += cs) {
+            int32_t p = rr.x + c * kChunk;
+            const bool more = c == nch - 1;
+            while (p < e) {
+                const int32_t j0 = p + lane < e ? A.itmS[p + lane] : INT32_MAX;
+                const int32_t j1 = p + kWave + lane < e ? A.itmS[p + kWave + lane] : INT32_MAX;
+                const int32_t j2 = p + 2 * kWave + lane < e ? A.itmS[p + 2 * kWave + lane] : INT32_MAX;
+                const int32_t j3 = p + 3 * kWave + lane < e ? A.itmS[p + 3 * kWave + lane] : INT32_MAX;
+                ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
+                const int32_t n = __popcll(__ballot(j0 < R.hi)) + __popcll(__ballot(j1 < R.hi)) +
+                                  __popcll(__ballot(j2 < R.hi)) + __popcll(__ballot(j3 < R.hi));
+                got += n;
+                if (!more || n < kChunk) break;
+                p += kChunk;
+            }
+        }
+        if (lane == 0 && got) atomicAdd(&S.taken[r], got);
+        // next: this wave's next short run, then every long run
+        if (h < nshort) {
+            h += W;
+            if (h >= nshort) h = nshort;
+        } else {
+            ++h;
+        }
     }
-    if (!ok) S.misc[1] = 1;
+    if (!ok) S.misc[kMiscOverflow] = 1;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kR; ++i)
-        if (slot[i] >= 0) nc[i] = S.runs[slot[i]].x;
+        if (slot[i] >= 0) nc[i] = S.runs[slot[i]].x + S.taken[slot[i]];
 }
 
 // Zero table words [0, limit); `tab` is 16-byte aligned.
@@ -254,12 +345,14 @@ __device__ __forceinline__ uint32_t slot_count(uint32_t w, const Range &R) {
     return R.mul ? (w & R.cmask) : w;
 }
 
-// Extract the candidates with count >= s.  Count mode returns their number;
-// fill mode also writes (a, b, w) in b order at out + base.  Leaves the table
-// cleared.  Returns a block-uniform count.
+// Extract the candidates with count >= s and return their number
+// (block-uniform).  Fill mode writes (a, b, w) in b order at task_off[t] +
+// rel; stage mode reserves room in the pool, writes (b, w) there and logs the
+// range (or flags task t when the pool or the log is full).  Leaves the table
+// cleared.
 template <int NT>
 __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S, const Range &R,
-                                               int32_t a, bool fill, int64_t base) {
+                                               int32_t a, int32_t t, int64_t rel) {
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int32_t L = R.limit;
@@ -273,15 +366,79 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
         const uint32_t w = slot < r1 ? S.tab[slot] : 0u;
         mine += __popcll(__ballot(slot_count(w, R) >= s));
     }
-    if (lane == 0) S.misc[3 + wid] = mine;
+    if (lane == 0) S.misc[kMiscWave + wid] = mine;
     __syncthreads();
     int32_t run = 0, total = 0;
     for (int w = 0; w < W; ++w) {
-        const int32_t t = S.misc[3 + w];
-        if (w < wid) run += t;
-        total += t;
+        const int32_t tw = S.misc[kMiscWave + w];
+        if (w < wid) run += tw;
+        total += tw;
     }
-    if (fill && total) {
+    bool write = false;
+    int64_t base = 0;
+    int32_t *dst_a = nullptr, *dst_b = nullptr, *dst_w = nullptr;
+    if (total && A.mode == kModeFill) {
+        write = true;
+        base = A.task_off[t] + rel;
+        dst_a = A.out_a;
+        dst_b = A.out_b;
+        dst_w = A.out_w;
+    } else if (total && A.mode == kModeStage) {
+        if (threadIdx.x == 0) {
+            // Pool room and log slots come from chunks this workgroup reserved
+            // with one global atomic each (records of a chunk left unused stay
+            // zero, i.e. empty).
+            bool ok = true;
+            uint64_t off = S.pool_cur[0];
+            if (off + (uint64_t)total > S.pool_cur[1]) {
+                const uint64_t size = max((uint64_t)total, (uint64_t)A.pool_chunk);
+                off = atomicAdd(A.pool_head, (unsigned long long)size);
+                if (off + size <= (uint64_t)A.pool_cap) {
+                    S.pool_cur[1] = off + size;
+                } else if (off + (uint64_t)total <= (uint64_t)A.pool_cap) {
+                    S.pool_cur[1] = (uint64_t)A.pool_cap;
+                } else {
+                    ok = false;
+                    S.pool_cur[1] = 0;
+                }
+            }
+            int32_t rec = 0;
+            if (ok) {
+                S.pool_cur[0] = off + (uint64_t)total;
+                if (S.log_cur[0] >= S.log_cur[1]) {
+                    const int32_t r = atomicAdd(A.log_head, A.log_chunk);
+                    S.log_cur[0] = r;
+                    S.log_cur[1] = min(r + A.log_chunk, A.log_cap);
+                }
+                rec = S.log_cur[0];
+                ok = rec < S.log_cur[1];
+                if (ok) S.log_cur[0] = rec + 1;
+            }
+            if (ok) {
+                StageRec r;
+                r.off = (int64_t)off;
+                r.t = t;
+                r.rel = (int32_t)rel;
+                r.n = total;
+                r.pad = 0;
+                A.log[rec] = r;
+            } else if (atomicExch(&A.need[t], 1) == 0) {
+                atomicAdd(A.need_count, 1);
+            }
+            S.misc[kMiscStageOk] = ok ? 1 : 0;
+            S.misc[kMiscStageLo] = (int32_t)(uint32_t)(off & 0xffffffffull);
+            S.misc[kMiscStageHi] = (int32_t)(uint32_t)(off >> 32);
+        }
+        __syncthreads();
+        if (S.misc[kMiscStageOk]) {
+            write = true;
+            base = (int64_t)(((uint64_t)(uint32_t)S.misc[kMiscStageHi] << 32) |
+                             (uint64_t)(uint32_t)S.misc[kMiscStageLo]);
+            dst_b = A.pool_b;
+            dst_w = A.pool_w;
+        }
+    }
+    if (write) {
         for (int32_t i = r0; i < r1; i += kWave) {
             const int32_t slot = i + lane;
             const uint32_t w = slot < r1 ? S.tab[slot] : 0u;
@@ -292,31 +449,55 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                 int32_t pos = run + (int32_t)lanes_below(bal);
                 int32_t key;
                 if (R.mul) {
-                    // rank against the cluster around `slot`: entries before it
-                    // in the cluster move past it when their key is larger
+                    // rank against the cluster: full buckets before this one back
+                    // to (not including) a bucket with a free slot, this bucket,
+                    // and full buckets after it up to the first with a free slot
                     const uint32_t tag = w >> R.cb;
+                    const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
+                    const int32_t nb = L >> 2, bk = slot >> 2, ib = slot & 3;
                     int32_t left = 0, less = 0;
-                    for (int32_t q2 = slot - 1; q2 >= 0; --q2) {
-                        const uint32_t u = S.tab[q2];
-                        if (u == 0u) break;
-                        if ((u & R.cmask) >= s) {
-                            ++left;
-                            less += (u >> R.cb) < tag;
+                    {
+                        const uint4 qv = t4[bk];
+                        const uint32_t u[4] = {qv.x, qv.y, qv.z, qv.w};
+                        bool full = true;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            full &= u[i] != 0u;
+                            if (i != ib && (u[i] & R.cmask) >= s) {
+                                left += i < ib;
+                                less += (u[i] >> R.cb) < tag;
+                            }
+                        }
+                        for (int32_t b2 = bk + 1; full && b2 < nb; ++b2) {
+                            const uint4 rv = t4[b2];
+                            const uint32_t r[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                full &= r[i] != 0u;
+                                less += (r[i] & R.cmask) >= s && (r[i] >> R.cb) < tag;
+                            }
                         }
                     }
-                    for (int32_t q2 = slot + 1; q2 < L; ++q2) {
-                        const uint32_t u = S.tab[q2];
-                        if (u == 0u) break;
-                        if ((u & R.cmask) >= s && (u >> R.cb) < tag) ++less;
+                    for (int32_t b2 = bk - 1; b2 >= 0; --b2) {
+                        const uint4 lv = t4[b2];
+                        if (lv.x == 0u || lv.y == 0u || lv.z == 0u || lv.w == 0u) break;
+                        const uint32_t l[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if ((l[i] & R.cmask) >= s) {
+                                ++left;
+                                less += (l[i] >> R.cb) < tag;
+                            }
+                        }
                     }
                     pos += less - left;
                     key = R.lo + (int32_t)tag - 1;
                 } else {
                     key = R.lo + slot;
                 }
-                A.out_a[base + pos] = a;
-                A.out_b[base + pos] = key;
-                A.out_w[base + pos] = (int32_t)c;
+                if (dst_a) dst_a[base + pos] = a;
+                dst_b[base + pos] = key;
+                dst_w[base + pos] = (int32_t)c;
             }
             run += __popcll(bal);
         }
@@ -332,27 +513,27 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
 // pairs produced (block-uniform).
 template <int NT, int PAD, int RUNCAP>
 __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, int32_t a,
-                                             int32_t lo, int32_t hi, int32_t slots, int32_t cb,
-                                             int32_t k0, int32_t k1, int32_t (&cur)[kR],
-                                             const int32_t (&end)[kR], bool fill, int64_t base,
-                                             int64_t &passes) {
+                                             int32_t t, int32_t lo, int32_t hi, int32_t slots,
+                                             int32_t cb, int32_t k0, int32_t k1, int32_t (&cur)[kR],
+                                             const int32_t (&end)[kR], int64_t &passes) {
     if (threadIdx.x == 0) {
         S.stack[0] = make_int2(lo, hi);
-        S.misc[2] = 1;
+        S.misc[kMiscDepth] = 1;
     }
     __syncthreads();
     int64_t produced = 0;
     for (;;) {
         // every thread reads the stack before anyone may change it (the next
         // call's thread 0 rewrites it as soon as it leaves this loop)
-        const int32_t depth = S.misc[2];
+        const int32_t depth = S.misc[kMiscDepth];
         const int2 top = depth ? S.stack[depth - 1] : make_int2(0, 0);
         __syncthreads();
         if (depth == 0) break;
         if (threadIdx.x == 0) {
-            S.misc[2] = depth - 1;
-            S.misc[0] = 0;
-            S.misc[1] = 0;
+            S.misc[kMiscDepth] = depth - 1;
+            S.misc[kMiscRuns] = 0;
+            S.misc[kMiscLong] = 0;
+            S.misc[kMiscOverflow] = 0;
         }
         __syncthreads();
         const Range R = make_range(top.x, top.y, slots, PAD, cb);
@@ -361,9 +542,9 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
             int32_t nc[kR];
             insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, nc);
             ++passes;
-            split = S.misc[1] != 0;
+            split = S.misc[kMiscOverflow] != 0;
             if (!split) {
-                produced += tab_extract<NT>(A, S, R, a, fill, base + produced);
+                produced += tab_extract<NT>(A, S, R, a, t, produced);
 #pragma unroll
                 for (int i = 0; i < kR; ++i) cur[i] = nc[i];
                 continue;
@@ -375,10 +556,10 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
         __syncthreads();
         if (threadIdx.x == 0) {
             const int32_t mid = (int32_t)(((int64_t)top.x + top.y) / 2);
-            const int32_t d = S.misc[2];
+            const int32_t d = S.misc[kMiscDepth];
             S.stack[d] = make_int2(mid, top.y);
             S.stack[d + 1] = make_int2(top.x, mid);
-            S.misc[2] = d + 2;
+            S.misc[kMiscDepth] = d + 2;
         }
         __syncthreads();
     }
@@ -427,7 +608,7 @@ __device__ __forceinline__ void task_range(int32_t a, int32_t N, int32_t p, int3
 constexpr int kSmallPad = 64;
 constexpr int kSmallRunCap = 128;
 constexpr int kTaskPad = 64;
-constexpr int kTaskRunCap = 512;
+constexpr int kTaskRunCap = 256;
 constexpr int kStack = 64;
 
 // --------------------------------------------------------------- small
@@ -436,16 +617,23 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
     constexpr int LIM = kSmallSlots + kSmallPad;
     __shared__ __align__(16) uint32_t tab[LIM];
     __shared__ int2 runs[kSmallRunCap];
+    __shared__ int32_t taken[kSmallRunCap];
     __shared__ int2 stack[kStack];
-    __shared__ int32_t misc[8];
-    const Smem S{tab, runs, misc, stack};
-    const bool fill = A.task_off != nullptr;
+    __shared__ int32_t misc[kMiscWave + 1];
+    __shared__ uint64_t pool_cur[2];
+    __shared__ int32_t log_cur[2];
+    const Smem S{tab, runs, taken, misc, stack, pool_cur, log_cur};
+    if (threadIdx.x == 0) {
+        pool_cur[0] = pool_cur[1] = 0;
+        log_cur[0] = log_cur[1] = 0;
+    }
     tab_clear<kWave>(tab, LIM);
     const int32_t n_small = A.task_counts[0];
     int64_t passes = 0;
     __syncthreads();
     for (int32_t r = blockIdx.x; r < n_small; r += gridDim.x) {
         const int32_t t = A.small_tasks[r];
+        if (A.mode == kModeFill && A.need && !A.need[t]) continue;
         const int32_t a = A.task_item[t];
         const int64_t c = A.cost[a];
         // 2 W_a home slots (load <= 1/2), rounded up to whole waves
@@ -454,10 +642,9 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         int32_t cur[kR], end[kR];
         init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end);
-        const int64_t base = fill ? A.task_off[t] : 0;
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
-            A, S, a, a + 1, A.N, want, count_bits(k1 - k0), k0, k1, cur, end, fill, base, passes);
-        if (!fill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
+            A, S, a, t, a + 1, A.N, want, count_bits(k1 - k0), k0, k1, cur, end, passes);
+        if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
     }
     if (threadIdx.x == 0 && passes && A.passes)
@@ -471,11 +658,17 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
     constexpr int LIM = kTaskSlots + kTaskPad;
     __shared__ __align__(16) uint32_t tab[LIM];
     __shared__ int2 runs[kTaskRunCap];
+    __shared__ int32_t taken[kTaskRunCap];
     __shared__ int2 stack[kStack];
-    __shared__ int32_t misc[3 + NT / kWave + 1];
+    __shared__ int32_t misc[kMiscWave + NT / kWave];
     __shared__ int32_t sh_task;
-    const Smem S{tab, runs, misc, stack};
-    const bool fill = A.task_off != nullptr;
+    __shared__ uint64_t pool_cur[2];
+    __shared__ int32_t log_cur[2];
+    const Smem S{tab, runs, taken, misc, stack, pool_cur, log_cur};
+    if (threadIdx.x == 0) {
+        pool_cur[0] = pool_cur[1] = 0;
+        log_cur[0] = log_cur[1] = 0;
+    }
     tab_clear<NT>(tab, LIM);
     const int32_t n_groups = A.task_counts[1];
     int64_t passes = 0;
@@ -493,17 +686,21 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t p1 = min(P, p0 + A.tune.group_parts);
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
-        int32_t lo, hi;
-        task_range(a, A.N, p0, P, lo, hi);
         int32_t cur[kR], end[kR];
-        init_cursors<NT>(A, a, lo, k0, k1, cur, end);
+        bool fresh = true;  // cursors must be placed at the range start
         for (int32_t q = p0; q < p1; ++q) {
+            int32_t lo, hi;
             task_range(a, A.N, q, P, lo, hi);
             const int32_t t = t0 + (q - p0);
-            const int64_t base = fill ? A.task_off[t] : 0;
+            if (A.mode == kModeFill && A.need && !A.need[t]) {
+                fresh = true;
+                continue;
+            }
+            if (fresh) init_cursors<NT>(A, a, lo, k0, k1, cur, end);
+            fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
-                A, S, a, lo, hi, kTaskSlots, cb, k0, k1, cur, end, fill, base, passes);
-            if (!fill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
+                A, S, a, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, passes);
+            if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         }
         __syncthreads();
     }
@@ -547,6 +744,35 @@ __global__ void k_task_fill(const int64_t *cost, int32_t N, int32_t small_max, i
 
 __global__ void k_reset_queue(int32_t *q) { *q = 0; }
 
+// One wave per staged range (grid-stride): pool -> final (a, b, w).
+__global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = wave; r < n_rec; r += nwaves) {
+        const StageRec rec = A.log[r];
+        // every record was written by the stage pass; the checks guard the
+        // indices below all the same
+        if (rec.t < 0 || rec.t >= A.n_tasks || rec.n < 0 || rec.off < 0 ||
+            rec.off + rec.n > A.pool_cap) {
+            if (lane == 0) atomicOr(A.err, kErrInternal);
+            continue;
+        }
+        if (A.need[rec.t]) continue;
+        const int32_t a = A.task_item[rec.t];
+        const int64_t dst = A.task_off[rec.t] + rec.rel;
+        if (rec.rel < 0 || dst + rec.n > A.task_off[rec.t + 1]) {
+            if (lane == 0) atomicOr(A.err, kErrInternal);
+            continue;
+        }
+        for (int32_t i = lane; i < rec.n; i += kWave) {
+            A.out_a[dst + i] = a;
+            A.out_b[dst + i] = A.pool_b[rec.off + i];
+            A.out_w[dst + i] = A.pool_w[rec.off + i];
+        }
+    }
+}
+
 inline int grid_for(int64_t work, int per_block, int cap) {
     int64_t g = (work + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
@@ -582,6 +808,12 @@ hipError_t launch_count(hipStream_t st, const CountArgs &A) {
     k_reset_queue<<<1, 1, 0, st>>>(A.queue);
     const int gh = std::max(1, A.n_cu * A.tune.task_grid_per_cu);
     k_count_tasks<<<gh, kTaskThreads, 0, st>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_copy(hipStream_t st, const CountArgs &A, int32_t n_rec) {
+    if (n_rec <= 0) return hipSuccess;
+    k_stage_copy<<<grid_for((int64_t)n_rec * kWave, 256, 16384), 256, 0, st>>>(A, n_rec);
     return hipGetLastError();
 }
 

@@ -22,11 +22,12 @@ enum : int32_t {
 // Tunable launch parameters of the counting kernels (the autotuner sets them).
 struct Tuning {
     int32_t small_max_wedges = 512;  // items with W_a up to this go to the one-wave kernel
-    int32_t task_wedges = 3600;      // wedges per workgroup task (j sub-range of an item)
+    int32_t task_wedges = 5000;      // wedges per workgroup task (j sub-range of an item)
     int32_t group_parts = 8;         // consecutive tasks of one item run by one workgroup
     int32_t light_len = 8;           // member runs up to this are walked by one lane
     int32_t small_grid_per_cu = 16;  // one-wave workgroups per CU for the small kernel
     int32_t task_grid_per_cu = 4;    // resident workgroups per CU for the task kernel
+    int64_t stage_max_bytes = 96ll << 30;  // cap of the staging pool (one counting pass)
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -102,24 +103,55 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *big_tasks, int32_t *counts);
 
+// Counting-kernel modes.
+enum : int32_t {
+    kModeCount = 0,  // pairs per task only
+    kModeFill = 1,   // write (a, b, w) at task_off (only tasks flagged in `need`, if given)
+    kModeStage = 2,  // pairs per task, and each extracted range's (b, w) into the pool
+};
+
+// One staged range: `n` pairs of task `t` at pool[off], destined for
+// task_off[t] + rel.
+struct StageRec {
+    int64_t off;
+    int32_t t, rel, n, pad;
+};
+
 struct CountArgs {
+    int32_t mode;
     const int32_t *ptrI, *memI;  // item lists
     const int32_t *ptrS, *itmS;  // filtered membership lists
     int32_t N, s;
     const int64_t *cost;         // W_a per item
     const int32_t *start;        // back-pointers per item incidence (see launch_cost)
     const int32_t *task_item, *task_part;
+    int32_t n_tasks;
     const int32_t *small_tasks, *big_tasks;
     const int32_t *task_counts;  // [0] small tasks, [1] task groups
     int32_t *queue;              // big-task queue head (reset by the launcher)
     int32_t *task_cnt;           // count mode: pairs per task
     const int64_t *task_off;     // fill mode: output offset per task (nullptr = count mode)
     int32_t *out_a, *out_b, *out_w;
+    // stage mode: pool of (b, w) pairs and the range log; tasks that found no
+    // room are flagged in need[] (need_count counts them) for a fill pass
+    int32_t *pool_b, *pool_w;
+    int64_t pool_cap;
+    int64_t pool_chunk;          // pool pairs a workgroup reserves at a time
+    unsigned long long *pool_head;
+    StageRec *log;
+    int32_t log_cap;
+    int32_t log_chunk;           // log records a workgroup reserves at a time
+    int32_t *log_head;
+    int32_t *need;
+    int32_t *need_count;
     int64_t *passes;
     int32_t *err;
     Tuning tune;
     int32_t n_cu;
 };
 hipError_t launch_count(hipStream_t st, const CountArgs &a);
+
+// Copy staged ranges to their final place (skipping tasks flagged in need).
+hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);
 
 }  // namespace sl

@@ -51,6 +51,16 @@ class sline_stats(ctypes.Structure):
                 for k, _ in self._fields_}
 
 
+class sline_tuning(ctypes.Structure):
+    _fields_ = [("small_max_wedges", ctypes.c_int32), ("task_wedges", ctypes.c_int32),
+                ("group_parts", ctypes.c_int32), ("light_len", ctypes.c_int32),
+                ("small_grid_per_cu", ctypes.c_int32), ("task_grid_per_cu", ctypes.c_int32),
+                ("stage_max_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -76,6 +86,8 @@ SIGNATURES = {
                                      ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
     "sline_edges_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
     "sline_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_stats)]),
+    "sline_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
+    "sline_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
     "sline_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "sline_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
@@ -130,6 +142,18 @@ def sline_last_stats(ctx) -> sline_stats:
     st = sline_stats()
     load().sline_last_stats(ctx, ctypes.byref(st))
     return st
+
+
+def sline_get_tuning(ctx) -> sline_tuning:
+    t = sline_tuning()
+    st = load().sline_get_tuning(ctx, ctypes.byref(t))
+    if st != SLINE_OK:
+        raise SlineError(st, "sline_get_tuning failed")
+    return t
+
+
+def sline_set_tuning(ctx, tuning: sline_tuning) -> int:
+    return load().sline_set_tuning(ctx, ctypes.byref(tuning))
 
 
 def sline_last_error(ctx) -> str:
@@ -231,3 +255,16 @@ class Context:
 
     def stats(self) -> dict:
         return sline_last_stats(self.ctx).as_dict()
+
+    def tuning(self) -> dict:
+        return sline_get_tuning(self.ctx).as_dict()
+
+    def set_tuning(self, **kw) -> None:
+        t = sline_get_tuning(self.ctx)
+        for k, v in kw.items():
+            if not hasattr(t, k):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        st = sline_set_tuning(self.ctx, t)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))

@@ -203,3 +203,38 @@ def test_wide_items_and_long_member_lists(ctx, dev):
         L = ctx.build(rp, col, g.n_vertices, s, dual)
         ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, threads=8)
         assert_same(L, ref, f"wide s={s} dual={dual}")
+
+
+def test_tuning_changes_speed_not_result(ctx, dev):
+    """Launch parameters (including a staging pool too small for the result,
+    which forces tasks to be counted again) never change the output."""
+    g = gen.powerlaw_1m(scale=0.01)
+    rp, col = to_device(g, dev)
+    base = ctx.tuning()
+    refs = {}
+    for s, dual in ((1, 0), (2, 0), (2, 1)):
+        refs[(s, dual)], _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s,
+                                          dual=dual, threads=8)
+    variants = [dict(stage_max_bytes=0), dict(stage_max_bytes=1 << 20),
+                dict(task_wedges=64, group_parts=1), dict(task_wedges=20000, group_parts=64),
+                dict(small_max_wedges=0), dict(light_len=0), dict(light_len=64),
+                dict(small_grid_per_cu=1, task_grid_per_cu=1)]
+    try:
+        for v in variants:
+            ctx.set_tuning(**{**base, **v})
+            for (s, dual), ref in refs.items():
+                print(f"case: tuning {v} s={s} dual={dual}", flush=True)
+                L = ctx.build(rp, col, g.n_vertices, s, dual)
+                assert_same(L, ref, f"tuning {v} s={s} dual={dual}")
+    finally:
+        ctx.set_tuning(**base)
+
+
+def test_tuning_rejects_out_of_range(ctx):
+    from paper_2010_11448_amd import sline
+    base = ctx.tuning()
+    for bad in (dict(task_wedges=1), dict(small_max_wedges=100000), dict(group_parts=0),
+                dict(stage_max_bytes=-1)):
+        with pytest.raises(sline.SlineError):
+            ctx.set_tuning(**{**base, **bad})
+    assert ctx.tuning() == base
