@@ -49,7 +49,8 @@ namespace sl {
 
 namespace {
 
-constexpr int kR = 8;  // member cursors per thread held in registers
+constexpr int kR = 8;        // member cursors per thread held in registers
+constexpr int kPiece = 256;  // planned entries per piece of a long member run
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
@@ -197,11 +198,10 @@ struct Smem {
     int32_t *log_cur;    // [next, end) of this workgroup's log chunk
 };
 
-// misc words: short-run count, overflow flag, stack depth, staging
-// reservation (ok, offset low, offset high), long-run count, then one word
-// per wave.
+// misc words: run pieces, overflow flag, stack depth, staging reservation
+// (ok, offset low, offset high), then one word per wave.
 constexpr int kMiscRuns = 0, kMiscOverflow = 1, kMiscDepth = 2, kMiscStageOk = 3,
-              kMiscStageLo = 4, kMiscStageHi = 5, kMiscLong = 6, kMiscWave = 7;
+              kMiscStageLo = 4, kMiscStageHi = 5, kMiscWave = 6;
 
 // One member's walk over [cur, end) of N_s(v) for the range R, one lane:
 // reads four entries at a time and stops at the first id >= R.hi.  Returns
@@ -250,19 +250,19 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
             const float est = (float)(end[i] - cur[i]) * frac;
             int32_t sl = -1;
             if (est > light) {
-                // short runs (one 256-entry chunk expected) take the first half
-                // of the run list, long runs the second half
-                constexpr int32_t half = RUNCAP / 2;
-                if (est * 1.25f + 32.0f < (float)(4 * kWave)) {
-                    sl = atomicAdd(&S.misc[kMiscRuns], 1);
-                    sl = sl < half ? sl : -1;
+                // K pieces of 256 planned entries (the last one open-ended)
+                const int32_t K = min(16, (int32_t)((est * 1.25f + 16.0f) * (1.0f / kPiece)) + 1);
+                const int32_t s0 = atomicAdd(&S.misc[kMiscRuns], K);
+                if (s0 + K <= RUNCAP) {
+                    for (int32_t k = 0; k < K; ++k) {
+                        const int32_t b = cur[i] + k * kPiece;
+                        S.runs[s0 + k] = make_int2(b, k == K - 1 ? end[i] : min(end[i], b + kPiece));
+                        S.taken[s0 + k] = 0;
+                    }
+                    sl = s0 | (K << 16);
                 } else {
-                    sl = atomicAdd(&S.misc[kMiscLong], 1);
-                    sl = sl < half ? half + sl : -1;
-                }
-                if (sl >= 0) {
-                    S.runs[sl] = make_int2(cur[i], end[i]);
-                    S.taken[sl] = 0;
+                    // no room: blank the slots this reservation holds, walk by lane
+                    for (int32_t k = s0; k < min(s0 + K, RUNCAP); ++k) S.runs[k] = make_int2(0, 0);
                 }
             }
             if (sl < 0) nc[i] = walk_lane(A.itmS, cur[i], end[i], R, S, ok);
@@ -277,59 +277,57 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
         walk_lane(A.itmS, b, e0, R, S, ok);
     }
     __syncthreads();
-    // Runs are walked 256 entries at a time.  Short runs (one chunk expected)
-    // go to the waves in turn; a long run is cut into chunks sized by its
-    // expected length, shared by all waves.  The entries below R.hi form a
-    // prefix of the run, so the chunk counts add up to it; the wave holding
-    // the last planned chunk continues while the run goes on.  (A run that
-    // found its half of the list full was walked by its own lane.)
-    constexpr int32_t kChunk = 4 * kWave;
-    constexpr int32_t half = RUNCAP / 2;
-    const int32_t nshort = min(S.misc[kMiscRuns], half);
-    const int32_t nlong = min(S.misc[kMiscLong], half);
-    for (int32_t h = wid < nshort ? wid : nshort; h < nshort + nlong;) {
-        const bool is_long = h >= nshort;
-        const int32_t r = is_long ? half + (h - nshort) : h;
-        const int2 rr = S.runs[r];
-        const int32_t e = rr.y;
-        int32_t nch = 1, c0 = 0, cs = 1;
-        if (is_long) {
-            const float est = (float)(e - rr.x) * frac;
-            nch = max(1, (int32_t)((est * 1.25f + 32.0f) * (1.0f / kChunk)) + 1);
-            c0 = (wid + W - (h % W)) % W;
-            cs = W;
-        }
-        int32_t got = 0;
-        for (int32_t c = c0; c < nch; c += cs) {
-            int32_t p = rr.x + c * kChunk;
-            const bool more = c == nch - 1;
-            while (p < e) {
-                const int32_t j0 = p + lane < e ? A.itmS[p + lane] : INT32_MAX;
-                const int32_t j1 = p + kWave + lane < e ? A.itmS[p + kWave + lane] : INT32_MAX;
-                const int32_t j2 = p + 2 * kWave + lane < e ? A.itmS[p + 2 * kWave + lane] : INT32_MAX;
-                const int32_t j3 = p + 3 * kWave + lane < e ? A.itmS[p + 3 * kWave + lane] : INT32_MAX;
-                ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
-                const int32_t n = __popcll(__ballot(j0 < R.hi)) + __popcll(__ballot(j1 < R.hi)) +
-                                  __popcll(__ballot(j2 < R.hi)) + __popcll(__ballot(j3 < R.hi));
-                got += n;
-                if (!more || n < kChunk) break;
-                p += kChunk;
+    // Pieces: each wave keeps four in flight (one 64-entry load each per
+    // step), taking pieces h = wid, wid + W, ... in turn.  The entries below
+    // R.hi form a prefix of a member's run, so the pieces' counts add up to it.
+    const int32_t npiece = min(S.misc[kMiscRuns], RUNCAP);
+    int32_t next = wid;
+    int32_t pr[4], pp[4], pe[4], pg[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pr[k] = -1;
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (pr[k] < 0 && next < npiece) {
+                const int2 rr = S.runs[next];
+                pr[k] = next;
+                pp[k] = rr.x;
+                pe[k] = rr.y;
+                pg[k] = 0;
+                next += W;
             }
+            any |= pr[k] >= 0;
         }
-        if (lane == 0 && got) atomicAdd(&S.taken[r], got);
-        // next: this wave's next short run, then every long run
-        if (h < nshort) {
-            h += W;
-            if (h >= nshort) h = nshort;
-        } else {
-            ++h;
+        if (!any) break;
+        int32_t j[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            j[k] = (pr[k] >= 0 && pp[k] + lane < pe[k]) ? A.itmS[pp[k] + lane] : INT32_MAX;
+        ok &= tab_add4(S.tab, R, j[0], j[1], j[2], j[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (pr[k] < 0) continue;
+            const int32_t n = __popcll(__ballot(j[k] < R.hi));
+            pg[k] += n;
+            pp[k] += kWave;
+            if (n < kWave || pp[k] >= pe[k]) {
+                if (lane == 0 && pg[k]) S.taken[pr[k]] = pg[k];
+                pr[k] = -1;
+            }
         }
     }
     if (!ok) S.misc[kMiscOverflow] = 1;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kR; ++i)
-        if (slot[i] >= 0) nc[i] = S.runs[slot[i]].x + S.taken[slot[i]];
+    for (int i = 0; i < kR; ++i) {
+        if (slot[i] >= 0) {
+            const int32_t s0 = slot[i] & 0xffff, K = slot[i] >> 16;
+            int32_t t = S.runs[s0].x;
+            for (int32_t k = 0; k < K; ++k) t += S.taken[s0 + k];
+            nc[i] = t;
+        }
+    }
 }
 
 // Zero table words [0, limit); `tab` is 16-byte aligned.
@@ -532,7 +530,6 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
         if (threadIdx.x == 0) {
             S.misc[kMiscDepth] = depth - 1;
             S.misc[kMiscRuns] = 0;
-            S.misc[kMiscLong] = 0;
             S.misc[kMiscOverflow] = 0;
         }
         __syncthreads();
