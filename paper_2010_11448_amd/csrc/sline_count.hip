@@ -142,21 +142,20 @@ __device__ __forceinline__ bool tab_probe(uint32_t *tab, const Range &R, uint32_
     }
 }
 
-// Count one wedge ending at candidate j.  Returns false if the probe ran off
-// the table (the caller splits the range).
-__device__ __forceinline__ bool tab_add(uint32_t *tab, const Range &R, int32_t j) {
-    const uint32_t x = (uint32_t)(j - R.lo);
-    if (x >= R.span) return true;  // outside the range: only with unsorted input (SKIP_VALIDATE)
-    if (R.mul == 0) {
-        atomicAdd(&tab[x], 1u);
-        return true;
-    }
-    const int32_t b = (int32_t)__umulhi(x, R.mul);
-    return tab_probe(tab, R, (x + 1u) << R.cb, b, reinterpret_cast<const uint4 *>(tab)[b]);
+// Pick word i of a bucket (i in 0..3) without indexing registers dynamically.
+__device__ __forceinline__ uint32_t pick4(int32_t i, uint32_t a0, uint32_t a1, uint32_t a2,
+                                          uint32_t a3) {
+    return i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : a3;
 }
 
-// Count up to four wedges (a candidate >= R.hi means none); the home buckets
-// are read together before any of them is resolved.
+// Count up to four wedges (a candidate >= R.hi means none).  The four home
+// buckets are read together; every wedge that finds its key there is counted
+// with one atomic add and every new key is claimed with one compare-and-swap,
+// all four swaps in flight before any result is looked at.  Buckets fill
+// front to back (a key always takes the first free word), so a bucket's used
+// words are a prefix.  Wedges whose home bucket is full, or whose free word was
+// taken by another key meanwhile, finish in the probe loop (rare at the load
+// factors the range splitting keeps).
 __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t j0, int32_t j1,
                                          int32_t j2, int32_t j3) {
     const int32_t j[4] = {j0, j1, j2, j3};
@@ -173,18 +172,67 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
             if (in[i]) atomicAdd(&tab[x[i]], 1u);
         return true;
     }
+    const uint32_t hmask = ~R.cmask;
     const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
     int32_t b[4];
+    uint32_t tag[4];
     uint4 q[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         b[i] = in[i] ? (int32_t)__umulhi(x[i], R.mul) : 0;
-        if (in[i]) q[i] = t4[b[i]];
+        tag[i] = (x[i] + 1u) << R.cb;
+        q[i] = in[i] ? t4[b[i]] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // first pass: add to a found key, or claim the first free word
+    uint32_t addr[4], old[4];
+    uint32_t pend = 0;  // bit i: wedge i issued a compare-and-swap
+    uint32_t slow = 0;  // bit i: wedge i continues in the probe loop
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t w0 = q[i].x, w1 = q[i].y, w2 = q[i].z, w3 = q[i].w;
+        const int32_t used = (w0 != 0u) + (w1 != 0u) + (w2 != 0u) + (w3 != 0u);
+        int32_t hit = -1;
+        if (w3 != 0u && (w3 & hmask) == tag[i]) hit = 3;
+        if (w2 != 0u && (w2 & hmask) == tag[i]) hit = 2;
+        if (w1 != 0u && (w1 & hmask) == tag[i]) hit = 1;
+        if (w0 != 0u && (w0 & hmask) == tag[i]) hit = 0;
+        addr[i] = 4u * (uint32_t)b[i] + (uint32_t)(hit >= 0 ? hit : used);
+        old[i] = 0u;
+        if (in[i]) {
+            if (hit >= 0) {
+                atomicAdd(&tab[addr[i]], 1u);
+            } else if (used < 4) {
+                old[i] = atomicCAS(&tab[addr[i]], 0u, tag[i] | 1u);
+                pend |= 1u << i;
+            } else {
+                slow |= 1u << i;
+                b[i] += 1;  // home bucket full without the key: continue after it
+            }
+        }
+    }
+    // second pass: the swaps' results
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if ((pend >> i) & 1u) {
+            if (old[i] != 0u) {
+                if ((old[i] & hmask) == tag[i]) atomicAdd(&tab[addr[i]], 1u);
+                else slow |= 1u << i;  // another key took the word: look again
+            }
+        }
     }
     bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (in[i]) ok &= tab_probe(tab, R, (x[i] + 1u) << R.cb, b[i], q[i]);
+    const int32_t nb = R.limit >> 2;
+    while (slow) {
+        const int32_t i = __builtin_ctz(slow);
+        slow &= slow - 1u;
+        const int32_t bi = i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
+        const uint32_t ti = pick4(i, tag[0], tag[1], tag[2], tag[3]);
+        if (bi >= nb) {
+            ok = false;
+        } else {
+            ok &= tab_probe(tab, R, ti, bi, t4[bi]);
+        }
+    }
     return ok;
 }
 
@@ -235,8 +283,9 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const float frac = (float)R.span / (float)((int64_t)A.N - R.lo);
-    const float light = (float)A.tune.light_len;
+    const float light_len = (float)A.tune.light_len;
     bool ok = true;
+    uint32_t light = 0;  // bit i: member i is walked by this lane
     int32_t slot[kR];
 #pragma unroll
     for (int i = 0; i < kR; ++i) {
@@ -249,7 +298,7 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
         if (k < k1 && cur[i] < end[i]) {
             const float est = (float)(end[i] - cur[i]) * frac;
             int32_t sl = -1;
-            if (est > light) {
+            if (est > light_len) {
                 // K pieces of 256 planned entries (the last one open-ended)
                 const int32_t K = min(16, (int32_t)((est * 1.25f + 16.0f) * (1.0f / kPiece)) + 1);
                 const int32_t s0 = atomicAdd(&S.misc[kMiscRuns], K);
@@ -265,9 +314,23 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
                     for (int32_t k = s0; k < min(s0 + K, RUNCAP); ++k) S.runs[k] = make_int2(0, 0);
                 }
             }
-            if (sl < 0) nc[i] = walk_lane(A.itmS, cur[i], end[i], R, S, ok);
+            if (sl < 0) light |= 1u << i;
             slot[i] = sl;
         }
+    }
+    // members walked by their own lane, one at a time (one copy of the walk)
+    while (light) {
+        const uint32_t bit = light & (0u - light);  // lowest member still to walk
+        light ^= bit;
+        int32_t c = 0, e = 0;
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            c = (bit & (1u << r)) ? cur[r] : c;
+            e = (bit & (1u << r)) ? end[r] : e;
+        }
+        const int32_t n = walk_lane(A.itmS, c, e, R, S, ok);
+#pragma unroll
+        for (int r = 0; r < kR; ++r) nc[r] = (bit & (1u << r)) ? n : nc[r];
     }
     // members past the register window: locate the range by binary search
     for (int32_t k = k0 + (int32_t)threadIdx.x + kR * NT; k < k1; k += NT) {
@@ -343,26 +406,38 @@ __device__ __forceinline__ uint32_t slot_count(uint32_t w, const Range &R) {
     return R.mul ? (w & R.cmask) : w;
 }
 
+__device__ __forceinline__ bool bucket_full(const uint4 &q) {
+    return q.x != 0u && q.y != 0u && q.z != 0u && q.w != 0u;
+}
+
 // Extract the candidates with count >= s and return their number
-// (block-uniform).  Fill mode writes (a, b, w) in b order at task_off[t] +
-// rel; stage mode reserves room in the pool, writes (b, w) there and logs the
-// range (or flags task t when the pool or the log is full).  Leaves the table
-// cleared.
+// (block-uniform).  Each lane holds one bucket (four slots, one 16-byte LDS
+// read), so the order inside a bucket is settled in registers; only buckets
+// in a run of full buckets (or right after one) rank their entries against
+// the neighbouring buckets of the run.  Fill mode writes (a, b, w) in b order
+// at task_off[t] + rel; stage mode reserves room in the pool, writes (b, w)
+// there and logs the range (or flags task t when the pool or the log is
+// full).  Leaves the table cleared.
 template <int NT>
 __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S, const Range &R,
                                                int32_t a, int32_t t, int64_t rel) {
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int32_t L = R.limit;
-    const int32_t per_wave = ((L + W * kWave - 1) / (W * kWave)) * kWave;
-    const int32_t r0 = wid * per_wave;
-    const int32_t r1 = min(L, r0 + per_wave);
+    const int32_t nbk = (L + 3) >> 2;  // words past L are zero
+    const int32_t per_wave = ((nbk + W * kWave - 1) / (W * kWave)) * kWave;
+    const int32_t b0 = wid * per_wave;
+    const int32_t b1 = min(nbk, b0 + per_wave);
     const uint32_t s = (uint32_t)A.s;
+    const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
     int32_t mine = 0;
-    for (int32_t i = r0; i < r1; i += kWave) {
-        const int32_t slot = i + lane;
-        const uint32_t w = slot < r1 ? S.tab[slot] : 0u;
-        mine += __popcll(__ballot(slot_count(w, R) >= s));
+    for (int32_t i = b0; i < b1; i += kWave) {
+        const int32_t bk = i + lane;
+        const uint4 q = bk < b1 ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
+        const int32_t n = (slot_count(q.x, R) >= s) + (slot_count(q.y, R) >= s) +
+                          (slot_count(q.z, R) >= s) + (slot_count(q.w, R) >= s);
+        mine += __popcll(__ballot(n & 1)) + 2 * __popcll(__ballot(n & 2)) +
+                4 * __popcll(__ballot(n & 4));
     }
     if (lane == 0) S.misc[kMiscWave + wid] = mine;
     __syncthreads();
@@ -437,67 +512,101 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
         }
     }
     if (write) {
-        for (int32_t i = r0; i < r1; i += kWave) {
-            const int32_t slot = i + lane;
-            const uint32_t w = slot < r1 ? S.tab[slot] : 0u;
-            const uint32_t c = slot_count(w, R);
-            const bool q = c >= s;
-            const uint64_t bal = __ballot(q);
-            if (q) {
-                int32_t pos = run + (int32_t)lanes_below(bal);
-                int32_t key;
-                if (R.mul) {
-                    // rank against the cluster: full buckets before this one back
-                    // to (not including) a bucket with a free slot, this bucket,
-                    // and full buckets after it up to the first with a free slot
-                    const uint32_t tag = w >> R.cb;
-                    const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
-                    const int32_t nb = L >> 2, bk = slot >> 2, ib = slot & 3;
-                    int32_t left = 0, less = 0;
-                    {
-                        const uint4 qv = t4[bk];
-                        const uint32_t u[4] = {qv.x, qv.y, qv.z, qv.w};
-                        bool full = true;
+        // fullness of the bucket before this wave's block
+        bool prev_full = R.mul && b0 > 0 && b0 < b1 && bucket_full(t4[b0 - 1]);
+        for (int32_t i = b0; i < b1; i += kWave) {
+            const int32_t bk = i + lane;
+            const uint4 q = bk < b1 ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+            uint32_t c[4];
+            bool ok[4];
+            int32_t n = 0;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            full &= u[i] != 0u;
-                            if (i != ib && (u[i] & R.cmask) >= s) {
-                                left += i < ib;
-                                less += (u[i] >> R.cb) < tag;
-                            }
-                        }
-                        for (int32_t b2 = bk + 1; full && b2 < nb; ++b2) {
-                            const uint4 rv = t4[b2];
-                            const uint32_t r[4] = {rv.x, rv.y, rv.z, rv.w};
+            for (int k = 0; k < 4; ++k) {
+                c[k] = slot_count(wv[k], R);
+                ok[k] = c[k] >= s;
+                n += ok[k];
+            }
+            // exclusive prefix of n over the lanes
+            const uint64_t m0 = __ballot(n & 1), m1 = __ballot(n & 2), m2 = __ballot(n & 4);
+            const int32_t before = (int32_t)lanes_below(m0) + 2 * (int32_t)lanes_below(m1) +
+                                   4 * (int32_t)lanes_below(m2);
+            const int32_t step = __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
+            if (R.mul == 0) {
+                // dense: slot order is candidate order
+                int32_t pos = run + before;
 #pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                full &= r[i] != 0u;
-                                less += (r[i] & R.cmask) >= s && (r[i] >> R.cb) < tag;
-                            }
-                        }
+                for (int k = 0; k < 4; ++k) {
+                    if (ok[k]) {
+                        if (dst_a) dst_a[base + pos] = a;
+                        dst_b[base + pos] = R.lo + 4 * bk + k;
+                        dst_w[base + pos] = (int32_t)c[k];
+                        ++pos;
                     }
+                }
+            } else {
+                uint32_t tag[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) tag[k] = wv[k] >> R.cb;
+                // rank inside the bucket by candidate
+                int32_t rank[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    rank[k] = 0;
+#pragma unroll
+                    for (int k2 = 0; k2 < 4; ++k2)
+                        if (k2 != k) rank[k] += ok[k2] && tag[k2] < tag[k];
+                }
+                // runs of full buckets: a bucket ends a run unless it is full
+                const bool full = bucket_full(q) && bk < b1;
+                const uint64_t fm = __ballot(full);
+                const bool pf = lane ? ((fm >> (lane - 1)) & 1ull) != 0 : prev_full;
+                int32_t left = 0;
+                if (n && (full || pf)) {
+                    // full buckets before this one in the same run
                     for (int32_t b2 = bk - 1; b2 >= 0; --b2) {
                         const uint4 lv = t4[b2];
-                        if (lv.x == 0u || lv.y == 0u || lv.z == 0u || lv.w == 0u) break;
+                        if (!bucket_full(lv)) break;
                         const uint32_t l[4] = {lv.x, lv.y, lv.z, lv.w};
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if ((l[i] & R.cmask) >= s) {
+                        for (int k2 = 0; k2 < 4; ++k2) {
+                            if ((l[k2] & R.cmask) >= s) {
                                 ++left;
-                                less += (l[i] >> R.cb) < tag;
+                                const uint32_t tg = l[k2] >> R.cb;
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) rank[k] += tg < tag[k];
                             }
                         }
                     }
-                    pos += less - left;
-                    key = R.lo + (int32_t)tag - 1;
-                } else {
-                    key = R.lo + slot;
+                    // buckets after this one up to the first that is not full
+                    bool more = full;
+                    for (int32_t b2 = bk + 1; more && b2 < nbk; ++b2) {
+                        const uint4 rv = t4[b2];
+                        more = bucket_full(rv);
+                        const uint32_t r[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2) {
+                            if ((r[k2] & R.cmask) >= s) {
+                                const uint32_t tg = r[k2] >> R.cb;
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) rank[k] += tg < tag[k];
+                            }
+                        }
+                    }
                 }
-                if (dst_a) dst_a[base + pos] = a;
-                dst_b[base + pos] = key;
-                dst_w[base + pos] = (int32_t)c;
+                const int32_t pos = run + before - left;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (ok[k]) {
+                        const int32_t p = pos + rank[k];
+                        if (dst_a) dst_a[base + p] = a;
+                        dst_b[base + p] = R.lo + (int32_t)tag[k] - 1;
+                        dst_w[base + p] = (int32_t)c[k];
+                    }
+                }
+                prev_full = ((fm >> 63) & 1ull) != 0;
             }
-            run += __popcll(bal);
+            run += step;
         }
     }
     __syncthreads();
