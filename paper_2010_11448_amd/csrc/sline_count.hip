@@ -236,6 +236,54 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
     return ok;
 }
 
+// Count up to four wedges whose keys, if present, were inserted before (the
+// candidate cannot reach s without them, so an absent key is skipped).  Dense
+// ranges add unconditionally: a candidate counted only here stays below s.
+__device__ __forceinline__ void tab_look4(uint32_t *tab, const Range &R, int32_t j0, int32_t j1,
+                                          int32_t j2, int32_t j3) {
+    const int32_t j[4] = {j0, j1, j2, j3};
+    uint32_t x[4];
+    bool in[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x[i] = (uint32_t)(j[i] - R.lo);
+        in[i] = j[i] < R.hi && x[i] < R.span;
+    }
+    if (R.mul == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (in[i]) atomicAdd(&tab[x[i]], 1u);
+        return;
+    }
+    const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
+    const int32_t nb = R.limit >> 2;
+    uint32_t tag[4];
+    int32_t b[4];
+    uint4 q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        tag[i] = (x[i] + 1u) << R.cb;
+        b[i] = in[i] ? (int32_t)__umulhi(x[i], R.mul) : 0;
+        q[i] = in[i] ? t4[b[i]] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!in[i]) continue;
+        for (;;) {
+            const uint32_t w0 = q[i].x, w1 = q[i].y, w2 = q[i].z, w3 = q[i].w;
+            const bool h0 = (w0 ^ tag[i]) <= R.cmask, h1 = (w1 ^ tag[i]) <= R.cmask;
+            const bool h2 = (w2 ^ tag[i]) <= R.cmask, h3 = (w3 ^ tag[i]) <= R.cmask;
+            if (h0 || h1 || h2 || h3) {
+                atomicAdd(&tab[4 * b[i] + (h0 ? 0 : h1 ? 1 : h2 ? 2 : 3)], 1u);
+                break;
+            }
+            // a bucket with a free word ends the search: the key is absent
+            if (w3 == 0u || ++b[i] >= nb) break;
+            q[i] = t4[b[i]];
+        }
+    }
+}
+
 struct Smem {
     uint32_t *tab;       // table words
     int2 *runs;          // long member runs of the current range
@@ -255,14 +303,15 @@ constexpr int kMiscRuns = 0, kMiscOverflow = 1, kMiscDepth = 2, kMiscStageOk = 3
 // reads four entries at a time and stops at the first id >= R.hi.  Returns
 // the new cursor.
 __device__ __forceinline__ int32_t walk_lane(const int32_t *itmS, int32_t cur, int32_t end,
-                                             const Range &R, const Smem &S, bool &ok) {
+                                             const Range &R, const Smem &S, bool look, bool &ok) {
     int32_t p = cur;
     while (p < end) {
         const int32_t j0 = itmS[p];
         const int32_t j1 = (p + 1 < end) ? itmS[p + 1] : INT32_MAX;
         const int32_t j2 = (p + 2 < end) ? itmS[p + 2] : INT32_MAX;
         const int32_t j3 = (p + 3 < end) ? itmS[p + 3] : INT32_MAX;
-        ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
+        if (look) tab_look4(S.tab, R, j0, j1, j2, j3);
+        else ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
         const int32_t taken = (j0 < R.hi) + (j1 < R.hi) + (j2 < R.hi) + (j3 < R.hi);
         p += taken;
         if (taken < 4) break;
@@ -279,7 +328,8 @@ __device__ __forceinline__ int32_t walk_lane(const int32_t *itmS, int32_t cur, i
 template <int NT, int RUNCAP>
 __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, const Range &R,
                                              int32_t k0, int32_t k1, const int32_t (&cur)[kR],
-                                             const int32_t (&end)[kR], int32_t (&nc)[kR]) {
+                                             const int32_t (&end)[kR], uint32_t lookm, bool look,
+                                             int32_t (&nc)[kR]) {
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const float frac = (float)R.span / (float)((int64_t)A.N - R.lo);
@@ -290,12 +340,12 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
 #pragma unroll
     for (int i = 0; i < kR; ++i) {
         slot[i] = -1;
-        nc[i] = cur[i];
+        if (!look) nc[i] = cur[i];
     }
 #pragma unroll
     for (int i = 0; i < kR; ++i) {
         const int32_t k = k0 + (int32_t)threadIdx.x + i * NT;
-        if (k < k1 && cur[i] < end[i]) {
+        if (k < k1 && cur[i] < end[i] && (((lookm >> i) & 1u) != 0u) == look) {
             const float est = (float)(end[i] - cur[i]) * frac;
             int32_t sl = -1;
             if (est > light_len) {
@@ -328,16 +378,18 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
             c = (bit & (1u << r)) ? cur[r] : c;
             e = (bit & (1u << r)) ? end[r] : e;
         }
-        const int32_t n = walk_lane(A.itmS, c, e, R, S, ok);
+        const int32_t n = walk_lane(A.itmS, c, e, R, S, look, ok);
 #pragma unroll
         for (int r = 0; r < kR; ++r) nc[r] = (bit & (1u << r)) ? n : nc[r];
     }
     // members past the register window: locate the range by binary search
     for (int32_t k = k0 + (int32_t)threadIdx.x + kR * NT; k < k1; k += NT) {
+        const int32_t st = A.start[k];
+        if ((st < 0) != look) continue;
         const int32_t v = A.memI[k];
         const int32_t e0 = A.ptrS[v + 1];
-        const int32_t b = lower_bound(A.itmS, A.start[k], e0, R.lo);
-        walk_lane(A.itmS, b, e0, R, S, ok);
+        const int32_t b = lower_bound(A.itmS, st & kStartMask, e0, R.lo);
+        walk_lane(A.itmS, b, e0, R, S, look, ok);
     }
     __syncthreads();
     // Pieces: each wave keeps four in flight (one 64-entry load each per
@@ -367,7 +419,8 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             j[k] = (pr[k] >= 0 && pp[k] + lane < pe[k]) ? A.itmS[pp[k] + lane] : INT32_MAX;
-        ok &= tab_add4(S.tab, R, j[0], j[1], j[2], j[3]);
+        if (look) tab_look4(S.tab, R, j[0], j[1], j[2], j[3]);
+        else ok &= tab_add4(S.tab, R, j[0], j[1], j[2], j[3]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (pr[k] < 0) continue;
@@ -622,7 +675,8 @@ template <int NT, int PAD, int RUNCAP>
 __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, int32_t a,
                                              int32_t t, int32_t lo, int32_t hi, int32_t slots,
                                              int32_t cb, int32_t k0, int32_t k1, int32_t (&cur)[kR],
-                                             const int32_t (&end)[kR], int64_t &passes) {
+                                             const int32_t (&end)[kR], uint32_t lookm,
+                                             int64_t &passes) {
     if (threadIdx.x == 0) {
         S.stack[0] = make_int2(lo, hi);
         S.misc[kMiscDepth] = 1;
@@ -646,9 +700,16 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
         bool split = too_wide(R);
         if (!split) {
             int32_t nc[kR];
-            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, nc);
+            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, false, nc);
             ++passes;
             split = S.misc[kMiscOverflow] != 0;
+            if (!split && A.s > 1) {
+                // members marked lookup-only count candidates the others inserted
+                __syncthreads();
+                if (threadIdx.x == 0) S.misc[kMiscRuns] = 0;
+                __syncthreads();
+                insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nc);
+            }
             if (!split) {
                 produced += tab_extract<NT>(A, S, R, a, t, produced);
 #pragma unroll
@@ -675,7 +736,9 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
 // Cursors of the thread's members for a walk starting at candidate lo.
 template <int NT>
 __device__ __forceinline__ void init_cursors(const CountArgs &A, int32_t a, int32_t lo, int32_t k0,
-                                             int32_t k1, int32_t (&cur)[kR], int32_t (&end)[kR]) {
+                                             int32_t k1, int32_t (&cur)[kR], int32_t (&end)[kR],
+                                             uint32_t &lookm) {
+    lookm = 0;
 #pragma unroll
     for (int i = 0; i < kR; ++i) {
         const int32_t k = k0 + (int32_t)threadIdx.x + i * NT;
@@ -684,7 +747,9 @@ __device__ __forceinline__ void init_cursors(const CountArgs &A, int32_t a, int3
         if (k < k1) {
             const int32_t v = A.memI[k];
             const int32_t e = A.ptrS[v + 1];
-            int32_t c = A.start[k];
+            const int32_t st = A.start[k];
+            lookm |= (uint32_t)(st < 0) << i;
+            int32_t c = st & kStartMask;
             if (lo > a + 1) c = lower_bound(A.itmS, c, e, lo);
             cur[i] = c;
             end[i] = e;
@@ -747,9 +812,10 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         want = std::min(kSmallSlots, std::max(kWave, ((want + kWave - 1) / kWave) * kWave));
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         int32_t cur[kR], end[kR];
-        init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end);
+        uint32_t lookm;
+        init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end, lookm);
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
-            A, S, a, t, a + 1, A.N, want, count_bits(k1 - k0), k0, k1, cur, end, passes);
+            A, S, a, t, a + 1, A.N, want, count_bits(k1 - k0), k0, k1, cur, end, lookm, passes);
         if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
     }
@@ -793,6 +859,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
         int32_t cur[kR], end[kR];
+        uint32_t lookm = 0;
         bool fresh = true;  // cursors must be placed at the range start
         for (int32_t q = p0; q < p1; ++q) {
             int32_t lo, hi;
@@ -802,10 +869,10 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
                 fresh = true;
                 continue;
             }
-            if (fresh) init_cursors<NT>(A, a, lo, k0, k1, cur, end);
+            if (fresh) init_cursors<NT>(A, a, lo, k0, k1, cur, end, lookm);
             fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
-                A, S, a, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, passes);
+                A, S, a, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
             if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         }
         __syncthreads();

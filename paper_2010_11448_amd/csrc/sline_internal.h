@@ -91,6 +91,17 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
                        int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
                        int32_t *start, int64_t *totals);
 
+// Lookup-only members (insertion cutoff, s > 1): a candidate b with
+// |S_a & S_b| >= s lies in at least s of the lists N_s(v), v in S_a, so if up
+// to s - 1 members of a only count candidates that the other members inserted
+// before them, every such b is still counted exactly; the others stay below s
+// and are dropped.  The longest lists (most wedges) are chosen; the choice is
+// flagged in the sign bit of start[k].
+constexpr int32_t kStartMask = 0x7fffffff;
+constexpr int32_t kMaxLookup = 15;  // lookup-only members per item at most
+hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
+                              int32_t s, const int32_t *ptrS, int32_t *start);
+
 // Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
 // candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is
 // listed in small_tasks (W_a <= small_max) or big_tasks; counts[0] / [1]

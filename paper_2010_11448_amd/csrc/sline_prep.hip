@@ -372,6 +372,42 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
     }
 }
 
+// One wave per kept item: flag as lookup-only the min(s - 1, kMaxLookup)
+// members with the most candidates after a (ties to the lower incidence), by
+// setting the sign bit of start[k].  At least one member stays unflagged, as
+// |S_a| >= s for a kept item.
+__global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const int32_t *memI,
+                                                     int32_t N, int32_t s, const int32_t *ptrS,
+                                                     int32_t *start) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t a = wave; a < N; a += nwaves) {
+        const int32_t b = ptrI[a], e = ptrI[a + 1];
+        if (e - b < s) continue;
+        const int32_t rounds = min(min(s - 1, kMaxLookup), e - b - 1);
+        for (int32_t r = 0; r < rounds; ++r) {
+            // best unflagged member: most candidates, then lowest k
+            uint64_t best = 0;
+            for (int32_t k = b + lane; k < e; k += kWave) {
+                const int32_t st = start[k];
+                if (st < 0) continue;
+                const int32_t c = ptrS[memI[k] + 1] - st;
+                const uint64_t key = ((uint64_t)(uint32_t)c << 32) | (uint32_t)(INT32_MAX - k);
+                best = key > best ? key : best;
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint64_t o = __shfl_xor(best, d, kWave);
+                best = o > best ? o : best;
+            }
+            if ((best >> 32) == 0) break;  // no member with candidates left
+            const int32_t k = INT32_MAX - (int32_t)(uint32_t)best;
+            if (lane == 0) start[k] |= (int32_t)0x80000000u;
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -499,6 +535,14 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
     if (N <= 0) return hipSuccess;
     k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s, ptrS,
                                                                      itmS, cost, start, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
+                              int32_t s, const int32_t *ptrS, int32_t *start) {
+    if (N <= 0 || s <= 1) return hipSuccess;
+    k_mark_lookup<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s,
+                                                                           ptrS, start);
     return hipGetLastError();
 }
 
