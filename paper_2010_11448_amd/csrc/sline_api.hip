@@ -525,7 +525,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     // 6. wedge counts, tasks
     const Tuning tu = c->tune;
     hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, ptrS, itmS, L.cost, L.start, L.totals), "cost");
-    hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, ptrS, L.start), "lookup members");
+    hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, ptrS, L.start, L.cost), "lookup members");
     hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, L.ntask), "task count");
     hip_check(c, launch_scan_i32_to_i64(st, L.ntask, N, L.tbase, L.part64), "task scan");
     int64_t *h = c->host;

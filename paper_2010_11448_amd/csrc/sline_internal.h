@@ -96,11 +96,12 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
 // to s - 1 members of a only count candidates that the other members inserted
 // before them, every such b is still counted exactly; the others stay below s
 // and are dropped.  The longest lists (most wedges) are chosen; the choice is
-// flagged in the sign bit of start[k].
+// flagged in the sign bit of start[k], and cost[a] is lowered to the planning
+// cost max(W_a - flagged wedges, W_a / 3).
 constexpr int32_t kStartMask = 0x7fffffff;
 constexpr int32_t kMaxLookup = 15;  // lookup-only members per item at most
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                              int32_t s, const int32_t *ptrS, int32_t *start);
+                              int32_t s, const int32_t *ptrS, int32_t *start, int64_t *cost);
 
 // Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
 // candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is

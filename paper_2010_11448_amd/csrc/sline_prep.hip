@@ -375,10 +375,12 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
 // One wave per kept item: flag as lookup-only the min(s - 1, kMaxLookup)
 // members with the most candidates after a (ties to the lower incidence), by
 // setting the sign bit of start[k].  At least one member stays unflagged, as
-// |S_a| >= s for a kept item.
+// |S_a| >= s for a kept item.  The item's planning cost becomes the wedges of
+// its inserting members (they fill the table), but at least a third of W_a
+// (every wedge is still read).
 __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const int32_t *memI,
                                                      int32_t N, int32_t s, const int32_t *ptrS,
-                                                     int32_t *start) {
+                                                     int32_t *start, int64_t *cost) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -386,6 +388,7 @@ __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const 
         const int32_t b = ptrI[a], e = ptrI[a + 1];
         if (e - b < s) continue;
         const int32_t rounds = min(min(s - 1, kMaxLookup), e - b - 1);
+        int64_t flagged = 0;
         for (int32_t r = 0; r < rounds; ++r) {
             // best unflagged member: most candidates, then lowest k
             uint64_t best = 0;
@@ -404,6 +407,11 @@ __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const 
             if ((best >> 32) == 0) break;  // no member with candidates left
             const int32_t k = INT32_MAX - (int32_t)(uint32_t)best;
             if (lane == 0) start[k] |= (int32_t)0x80000000u;
+            flagged += (int64_t)(best >> 32);
+        }
+        if (lane == 0 && flagged) {
+            const int64_t w = cost[a];
+            cost[a] = max(w - flagged, (w + 2) / 3);
         }
     }
 }
@@ -539,10 +547,10 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
 }
 
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                              int32_t s, const int32_t *ptrS, int32_t *start) {
+                              int32_t s, const int32_t *ptrS, int32_t *start, int64_t *cost) {
     if (N <= 0 || s <= 1) return hipSuccess;
     k_mark_lookup<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s,
-                                                                           ptrS, start);
+                                                                           ptrS, start, cost);
     return hipGetLastError();
 }
 
