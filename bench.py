@@ -8,24 +8,35 @@ builds L_s(H) for every s in {1, 2, 4, 8, 16} with one plain sline_build call
 each (outputs stay on the device; they are freed before the next call).
 
 Printed: one JSON line with incidence entries/s over the whole step, the
-roofline of the counting stage (algorithmic bytes 12*nnz_s + 4*W_s + 12*|L_s|
-per build over the time of its counting kernels, HIP events on the library's
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+roofline of the dominant kernel (the workgroup counting kernel k_count_tasks:
+algorithmic bytes 12*nnz + 4*W + 8*P of the items it counts -- their
+incidences, wedges and the (b, w) pairs it stages -- over its run time, HIP
+events on the library's stream around that kernel alone) and the CPU oracle
+timed on a bounded sample of the same workload.  HBM traffic comes from the
+committed rocprofv3 counter summary of that kernel when the kernel source is
+unchanged since it was taken (else null).
 
-Other forms (--form): ``dual`` (the same graph's dual, s in {2, 8, 32}).
+Other forms (--form): ``dual`` (the same graph's dual, s in {2, 8, 32});
+``copy`` (a plain device copy of known size, the calibration run for the
+FETCH_SIZE / WRITE_SIZE counters).
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(ROOT, "paper_2010_11448_amd", "csrc", "sline_count.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_count_tasks_powerlaw_1Mx2M_traffic.md")
 
 
 def parse():
@@ -33,7 +44,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--form", default="plain", choices=["plain", "dual"])
+    p.add_argument("--form", default="plain", choices=["plain", "dual", "copy"])
     p.add_argument("--s", default=None, help="comma-separated s values")
     p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -45,18 +56,30 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
 
-def cpu_baseline(g, s_list, dual, rows_hint):
+def cpu_baseline(g, s_list, dual, rows_hint, budget_s=15.0):
     """The O1 oracle (all pairs, sorted merge) on a seeded sample of items.
 
     Rows a are drawn uniformly; the oracle compares each with every b > a,
-    so the sampled time scaled by N / rows estimates the full build."""
+    so the sampled time scaled by N / rows estimates the full build.  The
+    sample size is set from a short probe so the whole sweep takes about
+    `budget_s` seconds."""
     import oracle
 
     N = g.n_vertices if dual else g.n_edges
-    threads = os.cpu_count() or 1
+    threads = min(os.cpu_count() or 1, 16)
     rng = np.random.default_rng(12345)
-    nrows = rows_hint or max(threads * 8, 64)
-    rows = np.sort(rng.choice(N, size=min(nrows, N), replace=False)).astype(np.int32)
+    order = rng.permutation(N).astype(np.int32)
+    if rows_hint:
+        nrows = rows_hint
+    else:
+        probe = np.sort(order[:threads * 2])
+        t0 = time.perf_counter()
+        oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, s_list[0], dual=dual, rows=probe,
+                     threads=threads, keep=False)
+        per_row = max((time.perf_counter() - t0) / len(probe), 1e-6)
+        nrows = int(budget_s / (per_row * len(s_list)))
+    nrows = max(threads, min(nrows, N))
+    rows = np.sort(order[:nrows])
     est = 0.0
     spent = 0.0
     for s in s_list:
@@ -73,6 +96,46 @@ def cpu_baseline(g, s_list, dual, rows_hint):
                       f"scaled by N/rows to {est:.0f} s for the full sweep"}
 
 
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def committed_traffic(form):
+    """HBM bytes per launch of the task kernel from the committed counter
+    summary, if it was taken on the current kernel source and this form."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic_json: (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_sha") != kernel_sha() or rec.get("form") != form:
+        return None
+    return rec
+
+
+def copy_calibration(steps):
+    """A plain device copy of known size, for calibrating HBM counters."""
+    import torch
+
+    nbytes = 1 << 31
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    print(json.dumps({"form": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "ms": dt * 1e3, "GBps": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -84,6 +147,9 @@ def main():
 
     from paper_2010_11448_amd import gen, sline
 
+    if args.form == "copy":
+        copy_calibration(max(args.steps, 1))
+        return
     dev = torch.device("cuda", 0)
     dual = 1 if args.form == "dual" else 0
     s_list = tuple(int(x) for x in args.s.split(",")) if args.s else (
@@ -119,22 +185,23 @@ def main():
     value = len(s_list) * g.nnz / (ms_per_step / 1000.0)
 
     alg_bytes = 0.0
-    count_ms = 0.0
+    task_ms = 0.0
     launches = 0
     builds = {}
     for s in s_list:
         recs = per_s[s]
         times = [r[0] * 1000.0 for r in recs]
         st = recs[0][1]
-        b = 12.0 * st["nnz_kept"] + 4.0 * st["wedges"] + 12.0 * st["n_pairs"]
+        b = 12.0 * st["heavy_nnz"] + 4.0 * st["heavy_wedges"] + 8.0 * st["heavy_pairs"]
         for _, sr in recs:
             alg_bytes += b
-            count_ms += sr["ms_count"] + sr["ms_fill"]
+            task_ms += sr["ms_tasks"]
             launches += 1
         builds[str(s)] = {
             "p50_ms": pct(times, 50), "p99_ms": pct(times, 99),
             "pairs": st["n_pairs"], "wedges": st["wedges"], "kept_items": st["n_kept"],
-            "alg_bytes": b,
+            "task_kernel_alg_bytes": b, "ms_tasks": float(np.median([r[1]["ms_tasks"] for r in recs])),
+            "task_kernel_GBps": b / 1e6 / max(float(np.median([r[1]["ms_tasks"] for r in recs])), 1e-9),
             "ms_transpose": float(np.median([r[1]["ms_transpose"] for r in recs])),
             "ms_prepare": float(np.median([r[1]["ms_prepare"] for r in recs])),
             "ms_count": float(np.median([r[1]["ms_count"] for r in recs])),
@@ -142,7 +209,9 @@ def main():
             "ms_fill": float(np.median([r[1]["ms_fill"] for r in recs])),
             "heavy_items": st["n_heavy"], "small_items": st["n_small"], "passes": st["passes"],
         }
-    achieved = alg_bytes / 1e9 / (count_ms / 1000.0) if count_ms > 0 else 0.0
+    achieved = alg_bytes / 1e9 / (task_ms / 1000.0) if task_ms > 0 else 0.0
+    tr = committed_traffic(args.form if args.scale == 1.0 and not args.s else None)
+    traffic = tr["bytes_per_launch"] if tr else None
     line = {
         "metric": "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99",
         "value": value,
@@ -160,10 +229,12 @@ def main():
                    "n_edges": g.n_edges, "n_vertices": g.n_vertices, "nnz": g.nnz,
                    "s": list(s_list), "dual": dual, "builds_per_step": len(s_list)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "counting stage (k_count_small + k_count_heavy, count and fill passes)",
-                     "alg_bytes_per_build": "12*nnz_s + 4*W_s + 12*|L_s|",
-                     "launch_pairs": launches},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_count_tasks (workgroup counting kernel, one launch per build)",
+                     "alg_bytes_per_launch": "12*nnz + 4*W + 8*P over the items it counts",
+                     "alg_bytes_mean": alg_bytes / max(launches, 1),
+                     "ms_mean": task_ms / max(launches, 1), "launches": launches,
+                     "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if tr else None},
         "builds": builds,
     }
     ctx.close()

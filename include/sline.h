@@ -109,6 +109,11 @@ typedef struct {
     double ms_count;      /* count pass (counting kernels, pairs per item)        */
     double ms_scan;       /* exclusive scan of pairs per item                     */
     double ms_fill;       /* fill pass (counting kernels writing the pairs)       */
+    /* the workgroup counting kernel alone (its count or staging pass)        */
+    int64_t heavy_nnz;    /* incidences of the items it counted                   */
+    int64_t heavy_wedges; /* wedges it walked                                     */
+    int64_t heavy_pairs;  /* pairs it produced                                    */
+    double ms_tasks;      /* its run time (SLINE_PROFILE)                         */
 } sline_stats;
 
 /* Launch parameters of the counting stage (they change speed, never the

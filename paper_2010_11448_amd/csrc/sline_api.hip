@@ -195,7 +195,7 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
     L.queue = A.take<int32_t>(4);
     L.tcounts = A.take<int32_t>(4);
     L.totals = A.take<int64_t>(4);
-    L.passes = A.take<int64_t>(2);
+    L.passes = A.take<int64_t>(4);
     L.rowid = A.take<int32_t>(nnz);
     L.degT = A.take<int32_t>(n);
     L.ptrT = A.take<int32_t>(n + 1);
@@ -490,7 +490,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     hip_check(c, launch_fill_i32(st, L.seg, 4, 0), "zero classes");
     hip_check(c, launch_fill_i32(st, L.tcounts, 4, 0), "zero task counts");
     hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
-    hip_check(c, launch_fill_i64(st, L.passes, 2, 0), "zero passes");
+    hip_check(c, launch_fill_i64(st, L.passes, 4, 0), "zero passes");
 
     mark(c, 0);
     // 2. row ids and member checks (range checks always: they guard every later index)
@@ -599,12 +599,14 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.err = L.err;
     C.tune = tu;
     C.n_cu = c->n_cu;
-    hip_check(c, launch_count(st, C), "count pass");
+    hip_check(c, launch_count(st, C, c->profile ? c->ev[7] : nullptr), "count pass");
     mark(c, 3);
     hip_check(c, launch_scan_i32_to_i64(st, TL.cnt, T, TL.off, TL.part64), "pair scan");
     mark(c, 4);
     hip_check(c, hipMemcpyAsync(h + 0, TL.off + T, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read total");
     hip_check(c, hipMemcpyAsync(h + 4, L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read passes");
+    hip_check(c, hipMemcpyAsync(h + 9, L.passes + 1, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+              "read task kernel work");
     hip_check(c, hipMemcpyAsync(h + 5, L.tcounts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read task counts");
     hip_check(c, hipMemcpyAsync(h + 6, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
     hip_check(c, hipMemcpyAsync(h + 7, TL.ctrs, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read stage counters");
@@ -613,6 +615,9 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const int32_t *hb = reinterpret_cast<const int32_t *>(h + 5);
     const int32_t *hc = reinterpret_cast<const int32_t *>(h + 7);
     S.passes = h[4];
+    S.heavy_nnz = h[9];
+    S.heavy_wedges = h[10];
+    S.heavy_pairs = h[11];
     S.n_small = hb[0];
     S.n_heavy = hb[1];
     S.n_pairs = total;
@@ -620,6 +625,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         S.ms_transpose = span_ms(c, 0, 1);
         S.ms_prepare = span_ms(c, 1, 2);
         S.ms_count = span_ms(c, 2, 3);
+        S.ms_tasks = span_ms(c, 7, 3);
         S.ms_scan = span_ms(c, 3, 4);
     }
     if (reinterpret_cast<const int32_t *>(h + 6)[0] & kErrInternal) {

@@ -844,6 +844,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
     tab_clear<NT>(tab, LIM);
     const int32_t n_groups = A.task_counts[1];
     int64_t passes = 0;
+    int64_t my_wedges = 0, my_nnz = 0, my_pairs = 0;
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) sh_task = atomicAdd(A.queue, 1);
@@ -869,13 +870,32 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
                 fresh = true;
                 continue;
             }
-            if (fresh) init_cursors<NT>(A, a, lo, k0, k1, cur, end, lookm);
+            if (fresh) {
+                init_cursors<NT>(A, a, lo, k0, k1, cur, end, lookm);
+                if (q == 0 && A.mode != kModeFill) {
+                    // work figures of this kernel: the item's incidences and wedges
+#pragma unroll
+                    for (int i = 0; i < kR; ++i) my_wedges += end[i] - cur[i];
+                    for (int32_t k = k0 + (int32_t)threadIdx.x + kR * NT; k < k1; k += NT)
+                        my_wedges += A.ptrS[A.memI[k] + 1] - (A.start[k] & kStartMask);
+                    my_nnz += k1 - k0;
+                }
+            }
             fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
                 A, S, a, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
-            if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
+            if (A.mode != kModeFill && threadIdx.x == 0) {
+                A.task_cnt[t] = (int32_t)produced;
+                my_pairs += produced;
+            }
         }
         __syncthreads();
+    }
+    if (A.passes && A.mode != kModeFill) {
+        unsigned long long *wk = (unsigned long long *)A.passes;
+        if (my_wedges) atomicAdd(&wk[2], (unsigned long long)my_wedges);
+        if (threadIdx.x == 0 && my_nnz) atomicAdd(&wk[1], (unsigned long long)my_nnz);
+        if (threadIdx.x == 0 && my_pairs) atomicAdd(&wk[3], (unsigned long long)my_pairs);
     }
     if (threadIdx.x == 0 && passes && A.passes)
         atomicAdd((unsigned long long *)A.passes, (unsigned long long)passes);
@@ -972,13 +992,17 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
     return hipGetLastError();
 }
 
-hipError_t launch_count(hipStream_t st, const CountArgs &A) {
+hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
     if (A.N <= 0) return hipSuccess;
     const int gs = std::max(1, A.n_cu * A.tune.small_grid_per_cu);
     k_count_small<<<gs, kWave, 0, st>>>(A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_reset_queue<<<1, 1, 0, st>>>(A.queue);
+    if (mid) {
+        e = hipEventRecord(mid, st);
+        if (e != hipSuccess) return e;
+    }
     const int gh = std::max(1, A.n_cu * A.tune.task_grid_per_cu);
     k_count_tasks<<<gh, kTaskThreads, 0, st>>>(A);
     return hipGetLastError();

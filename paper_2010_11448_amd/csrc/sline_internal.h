@@ -156,12 +156,14 @@ struct CountArgs {
     int32_t *log_head;
     int32_t *need;
     int32_t *need_count;
-    int64_t *passes;
+    int64_t *passes;             // [0] table passes; task kernel work: [1] incidences,
+                                 // [2] wedges, [3] pairs (count and stage modes)
     int32_t *err;
     Tuning tune;
     int32_t n_cu;
 };
-hipError_t launch_count(hipStream_t st, const CountArgs &a);
+// `mid` (may be null) is recorded between the one-wave kernel and the task kernel.
+hipError_t launch_count(hipStream_t st, const CountArgs &a, hipEvent_t mid = nullptr);
 
 // Copy staged ranges to their final place (skipping tasks flagged in need).
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);

@@ -44,7 +44,9 @@ class sline_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("n_items", "nnz", "nnz_kept", "n_kept", "wedges", "n_pairs", "n_small",
                  "n_heavy", "passes")] + [(k, ctypes.c_double) for k in
-                ("ms_transpose", "ms_prepare", "ms_count", "ms_scan", "ms_fill")]
+                ("ms_transpose", "ms_prepare", "ms_count", "ms_scan", "ms_fill")] + [
+                (k, ctypes.c_int64) for k in ("heavy_nnz", "heavy_wedges", "heavy_pairs")] + [
+                ("ms_tasks", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
