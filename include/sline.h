@@ -162,6 +162,29 @@ void sline_destroy(sline_ctx *ctx);
 sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
                          uint32_t flags, sline_edges *out);
 
+/* Build L_{s[g]} of every hypergraph Hs[g] (dual[g] as in sline_build) in
+ * one pass of the counting pipeline: the graphs' items are numbered one after
+ * the other, every item is compared against its own graph's s, and the pairs
+ * are split back per graph (the result of graph g is exactly what
+ * sline_build(ctx, Hs[g], s[g], dual[g], ...) returns).  The method is that of
+ * sline_build (Sec. IV-B/IV-C); batching only changes how many launches a
+ * set of graphs costs.
+ *   n_graphs   >= 0 (0: nothing to do)
+ *   Hs, s, dual, outs   host arrays of n_graphs entries; the CSR arrays they
+ *              point at are device memory owned by the caller
+ *   outs[g]    as in sline_build: capacity 0 lets the library allocate graph
+ *              g's arrays (free each with sline_edges_free); capacity > 0
+ *              supplies caller buffers.  If any graph's buffers are too small
+ *              the call returns SLINE_ECAPACITY, sets n_pairs of every graph
+ *              and writes no pairs; an immediate retry with the same
+ *              arguments (larger buffers) reuses the computed result.
+ * Errors: SLINE_EINVAL if any graph is malformed (as in sline_build) or any
+ * s[g] < 1 / dual[g] not in {0, 1}; the combined item and member counts and
+ * incidences must each stay below 2^31.  Other codes as above. */
+sline_status sline_build_batch(sline_ctx *ctx, int32_t n_graphs, const sline_csr *Hs,
+                               const int32_t *s, const int32_t *dual, uint32_t flags,
+                               sline_edges *outs);
+
 /* Release the arrays of a library-allocated result and zero the struct.
  * Caller-owned buffers (capacity > 0) are not touched. */
 sline_status sline_edges_free(sline_ctx *ctx, sline_edges *edges);

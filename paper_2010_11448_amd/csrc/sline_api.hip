@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/sline.h"
 #include "sline_internal.h"
@@ -57,6 +58,18 @@ struct sline_ctx {
     // stage events (SLINE_PROFILE)
     hipEvent_t ev[8] = {};
     bool profile = false;
+    // batch result kept after SLINE_ECAPACITY for an immediate retry
+    struct BatchPending {
+        bool valid = false;
+        std::vector<sline_csr> H;
+        std::vector<int32_t> s, dual;
+        uint32_t flags = 0;
+        sline_edges comb{};          // combined result (library-owned)
+        std::vector<int64_t> off;    // first pair of each graph, n_graphs + 1
+        void *bws = nullptr;         // batch workspace (descriptors, item bases)
+        size_t bws_bytes = 0;
+        int64_t *ibase_dev = nullptr, *off_dev = nullptr;
+    } bpend;
 };
 
 namespace {
@@ -398,6 +411,16 @@ void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
     out->n_pairs = total;
 }
 
+// Per-item thresholds of a batch: every item carries its own s (s_item, on
+// the device), between s_min and s_max.  Null for a plain build.
+struct ItemS {
+    const int32_t *s_item = nullptr;
+    int32_t s_min = 1, s_max = 1;
+};
+
+sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
+                        sline_edges *out, const ItemS &IS);
+
 sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
                         sline_edges *out) {
     if (!out) {
@@ -426,7 +449,13 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     }
     c->pending.valid = false;
     release_pool(c);
+    ItemS IS;
+    IS.s_min = IS.s_max = s;
+    return build_core(c, H, s, dual, flags, out, IS);
+}
 
+sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
+                        sline_edges *out, const ItemS &IS) {
     c->profile = (flags & SLINE_PROFILE) != 0;
     const int64_t m = H.n_edges, n = H.n_vertices;
     if (m > 0 && !H.row_ptr) {
@@ -478,7 +507,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         if (out->capacity == 0) out->a = out->b = out->w = nullptr;
         return SLINE_OK;
     }
-    const bool filt = s > 1;
+    const bool filt = IS.s_max > 1;
     Arena sizing;
     plan_layout(sizing, m, n, nnz, N, M, filt);
     ensure_ws(c, sizing.off + 4096);
@@ -514,18 +543,24 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     // 5. s filter
     const int32_t *ptrS = ptrM, *itmS = itmM;
     if (filt) {
-        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, nullptr, L.cntS, nullptr),
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, IS.s_item, nullptr, L.cntS,
+                                   nullptr),
                   "filter count");
         hip_check(c, launch_scan_i32(st, L.cntS, M, L.ptrS, L.part32), "filter scan");
-        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, L.ptrS, L.cntS, L.itmS),
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, IS.s_item, L.ptrS, L.cntS,
+                                   L.itmS),
                   "filter fill");
         ptrS = L.ptrS;
         itmS = L.itmS;
     }
     // 6. wedge counts, tasks
     const Tuning tu = c->tune;
-    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, ptrS, itmS, L.cost, L.start, L.totals), "cost");
-    hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, ptrS, L.start, L.cost), "lookup members");
+    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, IS.s_item, ptrS, itmS, L.cost, L.start,
+                             L.totals),
+              "cost");
+    hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS, L.start,
+                                    L.cost),
+              "lookup members");
     hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, L.ntask), "task count");
     hip_check(c, launch_scan_i32_to_i64(st, L.ntask, N, L.tbase, L.part64), "task scan");
     int64_t *h = c->host;
@@ -551,7 +586,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
               "task fill");
     mark(c, 2);
     // 7. one counting pass: pairs per task, each range's pairs staged in a pool
-    const int64_t want_pool = S.wedges / s;  // every pair of L_s accounts for >= s wedges
+    const int64_t want_pool = S.wedges / IS.s_min;  // every pair of L_s accounts for >= s wedges
     const int64_t pool_cap = want_pool > 0 ? acquire_pool(c, want_pool) : 0;
     hip_check(c, launch_fill_i32(st, TL.need, T, 0), "zero flags");
     // unused records of a reserved log chunk must read as empty
@@ -568,6 +603,7 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.itmS = itmS;
     C.N = (int32_t)N;
     C.s = s;
+    C.s_item = IS.s_item;
     C.cost = L.cost;
     C.start = L.start;
     C.task_item = TL.item;
@@ -658,6 +694,342 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
 
 }  // namespace
 
+// ---------------------------------------------------------------- batches
+
+namespace {
+
+void drop_batch_pending(sline_ctx *c) {
+    auto &P = c->bpend;
+    if (P.comb.a) {
+        (void)hipStreamSynchronize(c->stream);
+        const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(P.comb.n_pairs, 1);
+        dev_free(c, P.comb.a, bytes);
+        dev_free(c, P.comb.b, bytes);
+        dev_free(c, P.comb.w, bytes);
+    }
+    if (P.bws) dev_free(c, P.bws, P.bws_bytes);
+    P = sline_ctx::BatchPending{};
+}
+
+bool same_batch(const sline_ctx::BatchPending &P, int32_t G, const sline_csr *Hs, const int32_t *s,
+                const int32_t *dual, uint32_t flags) {
+    if (!P.valid || (int32_t)P.H.size() != G || P.flags != flags) return false;
+    for (int32_t g = 0; g < G; ++g) {
+        const sline_csr &a = P.H[g], &b = Hs[g];
+        if (a.row_ptr != b.row_ptr || a.col_idx != b.col_idx || a.n_edges != b.n_edges ||
+            a.n_vertices != b.n_vertices || P.s[g] != s[g] || P.dual[g] != dual[g])
+            return false;
+    }
+    return true;
+}
+
+// Hand each graph its slice of the combined result (ids shifted back), into
+// caller buffers or freshly allocated ones; checks capacities first.
+sline_status batch_split(sline_ctx *c, int32_t G, sline_edges *outs) {
+    auto &P = c->bpend;
+    hipStream_t st = c->stream;
+    for (int32_t g = 0; g < G; ++g) {
+        const int64_t need = P.off[g + 1] - P.off[g];
+        if (outs[g].capacity > 0 && outs[g].capacity < need) {
+            for (int32_t h = 0; h < G; ++h) outs[h].n_pairs = P.off[h + 1] - P.off[h];
+            set_err(c, "capacity too small for at least one graph");
+            return SLINE_ECAPACITY;
+        }
+    }
+    std::vector<int32_t *> pa(G), pb(G), pw(G);
+    std::vector<char> owned(G, 0);
+    try {
+        for (int32_t g = 0; g < G; ++g) {
+            const int64_t need = P.off[g + 1] - P.off[g];
+            if (outs[g].capacity > 0) {
+                pa[g] = outs[g].a;
+                pb[g] = outs[g].b;
+                pw[g] = outs[g].w;
+            } else if (need > 0) {
+                const size_t bytes = sizeof(int32_t) * (size_t)need;
+                pa[g] = (int32_t *)dev_alloc(c, bytes);
+                pb[g] = (int32_t *)dev_alloc(c, bytes);
+                pw[g] = (int32_t *)dev_alloc(c, bytes);
+                owned[g] = 1;
+                if (!pa[g] || !pb[g] || !pw[g]) {
+                    set_err(c, "output allocation failed");
+                    throw Fail{SLINE_ENOMEM};
+                }
+            }
+        }
+        if (P.comb.n_pairs > 0) {
+            int32_t **ptrs = (int32_t **)dev_alloc(c, sizeof(int32_t *) * 3 * (size_t)G);
+            if (!ptrs) {
+                set_err(c, "output table allocation failed");
+                throw Fail{SLINE_ENOMEM};
+            }
+            std::vector<int32_t *> h(3 * (size_t)G);
+            for (int32_t g = 0; g < G; ++g) {
+                h[g] = pa[g];
+                h[G + g] = pb[g];
+                h[2 * G + g] = pw[g];
+            }
+            hipError_t e = hipMemcpyAsync(ptrs, h.data(), sizeof(int32_t *) * h.size(),
+                                          hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = launch_batch_split(st, P.ibase_dev, P.off_dev, G, P.comb.a, P.comb.b, P.comb.w,
+                                       P.comb.n_pairs, ptrs, ptrs + G, ptrs + 2 * G);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            dev_free(c, ptrs, sizeof(int32_t *) * 3 * (size_t)G);
+            hip_check(c, e, "batch split");
+        }
+    } catch (...) {
+        for (int32_t g = 0; g < G; ++g) {
+            if (!owned[g]) continue;
+            const size_t bytes = sizeof(int32_t) * (size_t)(P.off[g + 1] - P.off[g]);
+            dev_free(c, pa[g], bytes);
+            dev_free(c, pb[g], bytes);
+            dev_free(c, pw[g], bytes);
+        }
+        throw;
+    }
+    for (int32_t g = 0; g < G; ++g) {
+        outs[g].n_pairs = P.off[g + 1] - P.off[g];
+        if (outs[g].capacity == 0) {
+            outs[g].a = pa[g];
+            outs[g].b = pb[g];
+            outs[g].w = pw[g];
+        }
+    }
+    return SLINE_OK;
+}
+
+sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int32_t *s,
+                        const int32_t *dual, uint32_t flags, sline_edges *outs) {
+    if (G < 0 || (G > 0 && (!Hs || !s || !dual || !outs))) {
+        set_err(c, "invalid batch arguments");
+        return SLINE_EINVAL;
+    }
+    for (int32_t g = 0; g < G; ++g) {
+        const sline_csr &H = Hs[g];
+        if (s[g] < 1 || (dual[g] != 0 && dual[g] != 1) || H.n_edges < 0 || H.n_vertices < 0 ||
+            (H.n_edges > 0 && !H.row_ptr) || outs[g].capacity < 0 ||
+            (outs[g].capacity > 0 && (!outs[g].a || !outs[g].b || !outs[g].w))) {
+            set_err(c, "invalid arguments for graph %s", std::to_string(g).c_str());
+            return SLINE_EINVAL;
+        }
+    }
+    if (same_batch(c->bpend, G, Hs, s, dual, flags)) {
+        const sline_status r = batch_split(c, G, outs);
+        if (r == SLINE_OK) drop_batch_pending(c);
+        return r;
+    }
+    drop_batch_pending(c);
+    c->pending.valid = false;
+    if (G == 0) return SLINE_OK;
+    hipStream_t st = c->stream;
+    auto &P = c->bpend;
+    // 1. per-graph nnz and row_ptr[0] checks
+    std::vector<BatchGraph> gr(G);
+    int32_t s_min = INT32_MAX, s_max = 1;
+    for (int32_t g = 0; g < G; ++g) {
+        BatchGraph &d = gr[g];
+        d = BatchGraph{};
+        d.rp = Hs[g].row_ptr;
+        d.col = Hs[g].col_idx;
+        d.m = Hs[g].n_edges;
+        d.n = Hs[g].n_vertices;
+        d.dual = dual[g];
+        d.s = s[g];
+        s_min = std::min(s_min, s[g]);
+        s_max = std::max(s_max, s[g]);
+    }
+    // small workspace: descriptors, nnz, flags, item bases, pair offsets, dual lists
+    const size_t small = sizeof(BatchGraph) * G + 8 * (size_t)(4 * G + 16) + 4096;
+    P.bws_bytes = small;
+    P.bws = dev_alloc(c, small);
+    if (!P.bws) {
+        set_err(c, "batch workspace allocation failed");
+        throw Fail{SLINE_ENOMEM};
+    }
+    Arena W;
+    W.base = reinterpret_cast<char *>(P.bws);
+    BatchGraph *d_gr = W.take<BatchGraph>(G);
+    int64_t *d_nnz = W.take<int64_t>(G);
+    int32_t *d_err = W.take<int32_t>(4);
+    P.ibase_dev = W.take<int64_t>(G + 1);
+    P.off_dev = W.take<int64_t>(G + 1);
+    int64_t *d_dbase = W.take<int64_t>(G + 1);
+    int32_t *d_dual_ids = W.take<int32_t>(G);
+    hip_check(c, launch_fill_i32(st, d_err, 4, 0), "zero flags");
+    hip_check(c, hipMemcpyAsync(d_gr, gr.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, st),
+              "upload graphs");
+    hip_check(c, launch_batch_nnz(st, d_gr, G, d_nnz, d_err), "batch nnz");
+    std::vector<int64_t> nnz(G);
+    int32_t herr = 0;
+    hip_check(c, hipMemcpyAsync(nnz.data(), d_nnz, sizeof(int64_t) * G, hipMemcpyDeviceToHost, st),
+              "read nnz");
+    hip_check(c, hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "batch nnz");
+    if (herr) {
+        set_err(c, "row_ptr must start at 0 in every graph");
+        drop_batch_pending(c);
+        return SLINE_EINVAL;
+    }
+    // 2. bases on the host
+    std::vector<int64_t> ibase(G + 1), dbase;
+    std::vector<int32_t> dual_ids;
+    int64_t NI = 0, MT = 0, ZT = 0, E = 0, ZD = 0, VD = 0;
+    for (int32_t g = 0; g < G; ++g) {
+        BatchGraph &d = gr[g];
+        if (nnz[g] < 0 || (nnz[g] > 0 && (!d.col || d.n == 0))) {
+            set_err(c, "graph %s: bad nnz or missing col_idx", std::to_string(g).c_str());
+            drop_batch_pending(c);
+            return SLINE_EINVAL;
+        }
+        d.nnz = nnz[g];
+        d.ibase = NI;
+        d.mbase = MT;
+        ibase[g] = NI;
+        NI += d.dual ? d.n : d.m;
+        MT += d.dual ? d.m : d.n;
+        ZT += nnz[g];
+        if (d.dual) {
+            d.dbase = E;
+            d.dzbase = ZD;
+            d.vdbase = VD;
+            dual_ids.push_back(g);
+            dbase.push_back(E);
+            E += d.m;
+            ZD += nnz[g];
+            VD += d.n;
+        }
+    }
+    ibase[G] = NI;
+    dbase.push_back(E);
+    if (NI >= INT32_MAX || MT >= INT32_MAX || ZT >= INT32_MAX) {
+        set_err(c, "batch too large: combined items, members and incidences must stay below 2^31");
+        drop_batch_pending(c);
+        return SLINE_EINVAL;
+    }
+    const int32_t GD = (int32_t)dual_ids.size();
+    hip_check(c, hipMemcpyAsync(d_gr, gr.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, st),
+              "upload graphs");
+    hip_check(c, hipMemcpyAsync(P.ibase_dev, ibase.data(), sizeof(int64_t) * (G + 1),
+                                hipMemcpyHostToDevice, st),
+              "upload item bases");
+    if (GD > 0) {
+        hip_check(c, hipMemcpyAsync(d_dbase, dbase.data(), sizeof(int64_t) * (GD + 1),
+                                    hipMemcpyHostToDevice, st),
+                  "upload dual bases");
+        hip_check(c, hipMemcpyAsync(d_dual_ids, dual_ids.data(), sizeof(int32_t) * GD,
+                                    hipMemcpyHostToDevice, st),
+                  "upload dual ids");
+    }
+    // 3. XD and its transpose; 4. combined item CSR
+    Arena sz;
+    auto plan = [&](Arena &A, Layout &X, int32_t *&xrp, int32_t *&len, int32_t *&ptrC,
+                    int32_t *&memC, int32_t *&s_item) {
+        xrp = A.take<int32_t>(E + 1);
+        X.rowid = A.take<int32_t>(ZD);
+        X.colT = A.take<int32_t>(ZD);
+        X.degT = A.take<int32_t>(VD);
+        X.ptrT = A.take<int32_t>(VD + 1);
+        X.fillT = A.take<int32_t>(VD);
+        X.mid_list = A.take<int32_t>(VD);
+        X.big_list = A.take<int32_t>(VD);
+        X.seg = A.take<int32_t>(4);
+        X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>(VD, NI) + 1));
+        len = A.take<int32_t>(NI);
+        ptrC = A.take<int32_t>(NI + 1);
+        memC = A.take<int32_t>(ZT);
+        s_item = A.take<int32_t>(NI);
+        X.cntS = A.take<int32_t>(ZD);  // XD columns
+    };
+    Layout X{};
+    int32_t *xrp, *len, *ptrC, *memC, *s_item;
+    plan(sz, X, xrp, len, ptrC, memC, s_item);
+    void *big = dev_alloc(c, sz.off + 4096);
+    if (!big) {
+        set_err(c, "batch arrays allocation failed");
+        drop_batch_pending(c);
+        throw Fail{SLINE_ENOMEM};
+    }
+    const size_t big_bytes = sz.off + 4096;
+    sline_edges comb{};
+    try {
+        Arena A;
+        A.base = reinterpret_cast<char *>(big);
+        plan(A, X, xrp, len, ptrC, memC, s_item);
+        int32_t *xcol = X.cntS;
+        hip_check(c, launch_fill_i32(st, xcol, ZD, 0), "zero dual columns");
+        hip_check(c, launch_fill_i32(st, X.rowid, ZD, 0), "zero dual rows");
+        if (GD > 0 && E > 0) {
+            hip_check(c, launch_batch_concat(st, d_gr, d_dual_ids, d_dbase, GD, E, xrp, xcol, X.rowid,
+                                             d_err),
+                      "dual rows");
+            hip_check(c, launch_fill_i32(st, X.seg, 4, 0), "zero classes");
+            if (ZD > 0) transpose(c, X, xcol, (int32_t)VD, ZD);
+            else hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
+        } else if (VD > 0) {
+            hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
+        }
+        hip_check(c, launch_batch_len(st, d_gr, P.ibase_dev, G, NI, X.ptrT, len, s_item, d_err),
+                  "item lengths");
+        hip_check(c, launch_scan_i32(st, len, NI, ptrC, X.part32), "item scan");
+        hip_check(c, launch_batch_rows(st, d_gr, P.ibase_dev, G, NI, X.ptrT, X.colT, ptrC, memC, d_err),
+                  "item rows");
+        hip_check(c, hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "batch items");
+        if (herr) {
+            set_err(c, "a graph breaks the CSR rules (row_ptr order, member range or order)");
+            dev_free(c, big, big_bytes);
+            drop_batch_pending(c);
+            return SLINE_EINVAL;
+        }
+        // 5. one pass of the pipeline over the combined items, each with its own s
+        sline_csr CH{};
+        CH.row_ptr = ptrC;
+        CH.col_idx = memC;
+        CH.n_edges = (int32_t)NI;
+        CH.n_vertices = (int32_t)std::max<int64_t>(MT, 1);
+        ItemS IS;
+        IS.s_item = s_item;
+        IS.s_min = s_min;
+        IS.s_max = s_max;
+        const sline_status r =
+            build_core(c, CH, s_min, 0, flags | SLINE_SKIP_VALIDATE, &comb, IS);
+        if (r != SLINE_OK) {
+            dev_free(c, big, big_bytes);
+            drop_batch_pending(c);
+            return r;
+        }
+        release_pool(c);
+    } catch (...) {
+        dev_free(c, big, big_bytes);
+        drop_batch_pending(c);
+        throw;
+    }
+    dev_free(c, big, big_bytes);
+    // 6. per-graph slices
+    P.comb = comb;
+    P.off.assign(G + 1, 0);
+    if (comb.n_pairs > 0) {
+        hip_check(c, launch_batch_bounds(st, P.ibase_dev, G, comb.a, comb.n_pairs, P.off_dev),
+                  "graph bounds");
+        hip_check(c, hipMemcpyAsync(P.off.data(), P.off_dev, sizeof(int64_t) * (G + 1),
+                                    hipMemcpyDeviceToHost, st),
+                  "read graph bounds");
+        sync(c, "graph bounds");
+    }
+    P.H.assign(Hs, Hs + G);
+    P.s.assign(s, s + G);
+    P.dual.assign(dual, dual + G);
+    P.flags = flags;
+    P.valid = true;
+    const sline_status r = batch_split(c, G, outs);
+    if (r == SLINE_OK) drop_batch_pending(c);
+    return r;
+}
+
+}  // namespace
+
 extern "C" {
 
 sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const sline_allocator *alloc) {
@@ -699,6 +1071,7 @@ sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const s
 void sline_destroy(sline_ctx *c) {
     if (!c) return;
     release_pool(c);
+    drop_batch_pending(c);
     (void)hipStreamSynchronize(c->stream);
     if (c->ws) dev_free(c, c->ws, c->ws_bytes);
     if (c->ws2) dev_free(c, c->ws2, c->ws2_bytes);
@@ -724,6 +1097,29 @@ sline_status sline_build(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uin
         c->pending.valid = false;
         return f.st;
     } catch (const std::bad_alloc &) {
+        c->pending.valid = false;
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_build_batch(sline_ctx *c, int32_t n_graphs, const sline_csr *Hs, const int32_t *s,
+                               const int32_t *dual, uint32_t flags, sline_edges *outs) {
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return batch_impl(c, n_graphs, Hs, s, dual, flags, outs);
+    } catch (const Fail &f) {
+        drop_batch_pending(c);
+        c->pending.valid = false;
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        drop_batch_pending(c);
         c->pending.valid = false;
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;

@@ -1,0 +1,234 @@
+// Batched builds: many hypergraphs, each with its own s and role (primal or
+// dual), counted in one pass of the plain pipeline.
+//
+// The graphs are independent, so their items can share one id space: graph
+// g's items take the ids [ibase_g, ibase_g + N_g) and its members the ids
+// [mbase_g, mbase_g + M_g).  Two items of different graphs share no member,
+// so the combined L_s (each item compared with its own graph's s) is the
+// disjoint union of the graphs' L_s, and sorting by (a, b) keeps every
+// graph's pairs contiguous.  The kernels here build the combined item CSR
+// (checking every caller CSR on the way), give every item its graph's s,
+// and split the combined result back per graph.
+//
+// A dual graph's items are its vertices: their member lists are the rows of
+// H_g^T, built by transposing XD, the row concatenation of all dual graphs'
+// H_g (columns shifted by vdbase_g so the graphs' vertices do not collide).
+#include <algorithm>
+
+#include "sline_internal.h"
+
+namespace sl {
+
+namespace {
+
+inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
+    const int64_t g = (work + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// last g with base[g] <= x, for base ascending with base[0] = 0 <= x
+__device__ __forceinline__ int32_t find_graph(const int64_t *base, int32_t G, int64_t x) {
+    int32_t lo = 0, hi = G;  // base[lo] <= x < base[hi] (base[G] = total)
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Per graph: nnz (row_ptr[m]) and the row_ptr[0] == 0 check.
+__global__ void k_batch_nnz(const BatchGraph *gr, int32_t G, int64_t *nnz, int32_t *err) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const BatchGraph d = gr[g];
+    int64_t z = 0;
+    if (d.m > 0) {
+        if (d.rp[0] != 0) atomicOr(err, kErrRowPtr0);
+        z = d.rp[d.m];
+    }
+    nnz[g] = z;
+}
+
+// One wave per row of XD (the dual graphs' rows, in graph order): row
+// pointer, columns shifted by vdbase, row ids; range and order checks.
+__global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, const int32_t *dual_ids,
+                                                      const int64_t *dbase, int32_t GD, int64_t E,
+                                                      int32_t *xrp, int32_t *xcol, int32_t *xrow,
+                                                      int32_t *err) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t e = wave; e < E; e += nwaves) {
+        const int32_t q = find_graph(dbase, GD, e);
+        const BatchGraph d = gr[dual_ids[q]];
+        const int32_t loc = (int32_t)(e - dbase[q]);
+        const int32_t b = d.rp[loc], en = d.rp[loc + 1];
+        if (lane == 0) {
+            xrp[e] = (int32_t)(d.dzbase + b);
+            if (e == E - 1) xrp[E] = (int32_t)(d.dzbase + en);
+        }
+        // a row outside [0, nnz) is reported and never read (its entries of
+        // XD stay zero, so later kernels index safely until the error returns)
+        if (b < 0 || en < b || en > d.nnz) {
+            if (lane == 0) atomicOr(err, kErrRowPtrOrder);
+            continue;
+        }
+        int32_t bad = 0;
+        for (int32_t k = b + lane; k < en; k += kWave) {
+            const int32_t v = d.col[k];
+            if (v < 0 || v >= d.n) bad |= kErrColRange;
+            if (k > b && d.col[k - 1] >= v) bad |= kErrColOrder;
+            const int64_t o = d.dzbase + k;
+            xcol[o] = (v >= 0 && v < d.n) ? (int32_t)(d.vdbase + v) : 0;
+            xrow[o] = (int32_t)e;
+        }
+        if (bad) atomicOr(err, bad);
+    }
+}
+
+// One thread per combined item: its row length and its graph's s.
+__global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t G, int64_t NI,
+                            const int32_t *ptrT, int32_t *len, int32_t *s_item, int32_t *err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = find_graph(ibase, G, i);
+        const BatchGraph d = gr[g];
+        const int32_t loc = (int32_t)(i - ibase[g]);
+        int32_t l;
+        if (d.dual) {
+            const int64_t r = d.vdbase + loc;
+            l = ptrT[r + 1] - ptrT[r];
+        } else {
+            const int32_t b = d.rp[loc], en = d.rp[loc + 1];
+            l = en - b;
+            if (b < 0 || en < b || en > d.nnz) {
+                atomicOr(err, kErrRowPtrOrder);
+                l = 0;
+            }
+        }
+        len[i] = l;
+        s_item[i] = d.s;
+    }
+}
+
+// One wave per combined item: copy its members into the combined CSR with
+// the graph's member base (primal rows are checked here).
+__global__ __launch_bounds__(256) void k_batch_rows(const BatchGraph *gr, const int64_t *ibase,
+                                                    int32_t G, int64_t NI, const int32_t *ptrT,
+                                                    const int32_t *colT, const int32_t *ptrC,
+                                                    int32_t *memC, int32_t *err) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t i = wave; i < NI; i += nwaves) {
+        const int32_t g = find_graph(ibase, G, i);
+        const BatchGraph d = gr[g];
+        const int32_t loc = (int32_t)(i - ibase[g]);
+        const int32_t o = ptrC[i], l = ptrC[i + 1] - o;
+        if (d.dual) {
+            const int32_t src = ptrT[d.vdbase + loc];
+            for (int32_t k = lane; k < l; k += kWave)
+                memC[o + k] = (int32_t)(colT[src + k] - d.dbase + d.mbase);
+        } else {
+            const int32_t src = d.rp[loc];
+            int32_t bad = 0;
+            for (int32_t k = lane; k < l; k += kWave) {
+                const int32_t v = d.col[src + k];
+                if (v < 0 || v >= d.n) bad |= kErrColRange;
+                if (k > 0 && d.col[src + k - 1] >= v) bad |= kErrColOrder;
+                memC[o + k] = (v >= 0 && v < d.n) ? (int32_t)(d.mbase + v) : (int32_t)d.mbase;
+            }
+            if (bad) atomicOr(err, bad);
+        }
+    }
+}
+
+// One thread per graph: first pair of the graph in the combined result
+// (items of graph g are [ibase_g, ibase_{g+1}); `a` is sorted).
+__global__ void k_batch_bounds(const int64_t *ibase, int32_t G, const int32_t *a, int64_t P,
+                               int64_t *off) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > G) return;
+    if (g == G) {
+        off[G] = P;
+        return;
+    }
+    const int64_t key = ibase[g];
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    off[g] = lo;
+}
+
+// Grid-stride over the combined pairs: each goes to its graph's output with
+// the graph's item base taken off both ids.
+__global__ void k_batch_split(const int64_t *ibase, const int64_t *off, int32_t G,
+                              const int32_t *a, const int32_t *b, const int32_t *w, int64_t P,
+                              int32_t *const *oa, int32_t *const *ob, int32_t *const *ow) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = find_graph(off, G, k);
+        const int64_t r = k - off[g];
+        const int32_t base = (int32_t)ibase[g];
+        oa[g][r] = a[k] - base;
+        ob[g][r] = b[k] - base;
+        ow[g][r] = w[k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_nnz(hipStream_t st, const BatchGraph *gr, int32_t G, int64_t *nnz,
+                            int32_t *err) {
+    if (G <= 0) return hipSuccess;
+    k_batch_nnz<<<grid_for(G, 256), 256, 0, st>>>(gr, G, nnz, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32_t *dual_ids,
+                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xrp,
+                               int32_t *xcol, int32_t *xrow, int32_t *err) {
+    if (E <= 0) return hipSuccess;
+    k_batch_concat<<<grid_for(E * kWave, 256, 65536), 256, 0, st>>>(gr, dual_ids, dbase, GD, E, xrp,
+                                                                    xcol, xrow, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
+                            int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
+                            int32_t *err) {
+    if (NI <= 0) return hipSuccess;
+    k_batch_len<<<grid_for(NI, 256, 65536), 256, 0, st>>>(gr, ibase, G, NI, ptrT, len, s_item, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
+                             int64_t NI, const int32_t *ptrT, const int32_t *colT,
+                             const int32_t *ptrC, int32_t *memC, int32_t *err) {
+    if (NI <= 0) return hipSuccess;
+    k_batch_rows<<<grid_for(NI * kWave, 256, 65536), 256, 0, st>>>(gr, ibase, G, NI, ptrT, colT,
+                                                                   ptrC, memC, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, const int32_t *a,
+                               int64_t P, int64_t *off) {
+    k_batch_bounds<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(ibase, G, a, P, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,
+                              const int32_t *a, const int32_t *b, const int32_t *w, int64_t P,
+                              int32_t *const *oa, int32_t *const *ob, int32_t *const *ow) {
+    if (P <= 0) return hipSuccess;
+    k_batch_split<<<grid_for(P, 256, 65536), 256, 0, st>>>(ibase, off, G, a, b, w, P, oa, ob, ow);
+    return hipGetLastError();
+}
+
+}  // namespace sl

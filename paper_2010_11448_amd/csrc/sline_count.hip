@@ -473,7 +473,7 @@ __device__ __forceinline__ bool bucket_full(const uint4 &q) {
 // full).  Leaves the table cleared.
 template <int NT>
 __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S, const Range &R,
-                                               int32_t a, int32_t t, int64_t rel) {
+                                               int32_t a, int32_t sa, int32_t t, int64_t rel) {
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
     const int32_t L = R.limit;
@@ -481,7 +481,7 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
     const int32_t per_wave = ((nbk + W * kWave - 1) / (W * kWave)) * kWave;
     const int32_t b0 = wid * per_wave;
     const int32_t b1 = min(nbk, b0 + per_wave);
-    const uint32_t s = (uint32_t)A.s;
+    const uint32_t s = (uint32_t)sa;
     const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
     int32_t mine = 0;
     for (int32_t i = b0; i < b1; i += kWave) {
@@ -673,7 +673,8 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
 // pairs produced (block-uniform).
 template <int NT, int PAD, int RUNCAP>
 __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, int32_t a,
-                                             int32_t t, int32_t lo, int32_t hi, int32_t slots,
+                                             int32_t sa, int32_t t, int32_t lo, int32_t hi,
+                                             int32_t slots,
                                              int32_t cb, int32_t k0, int32_t k1, int32_t (&cur)[kR],
                                              const int32_t (&end)[kR], uint32_t lookm,
                                              int64_t &passes) {
@@ -703,7 +704,7 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
             insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, false, nc);
             ++passes;
             split = S.misc[kMiscOverflow] != 0;
-            if (!split && A.s > 1) {
+            if (!split && sa > 1) {
                 // members marked lookup-only count candidates the others inserted
                 __syncthreads();
                 if (threadIdx.x == 0) S.misc[kMiscRuns] = 0;
@@ -711,7 +712,7 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
                 insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nc);
             }
             if (!split) {
-                produced += tab_extract<NT>(A, S, R, a, t, produced);
+                produced += tab_extract<NT>(A, S, R, a, sa, t, produced);
 #pragma unroll
                 for (int i = 0; i < kR; ++i) cur[i] = nc[i];
                 continue;
@@ -815,7 +816,8 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         uint32_t lookm;
         init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end, lookm);
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
-            A, S, a, t, a + 1, A.N, want, count_bits(k1 - k0), k0, k1, cur, end, lookm, passes);
+            A, S, a, A.s_item ? A.s_item[a] : A.s, t, a + 1, A.N, want, count_bits(k1 - k0), k0,
+            k1, cur, end, lookm, passes);
         if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
     }
@@ -859,6 +861,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t p1 = min(P, p0 + A.tune.group_parts);
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
+        const int32_t sa = A.s_item ? A.s_item[a] : A.s;
         int32_t cur[kR], end[kR];
         uint32_t lookm = 0;
         bool fresh = true;  // cursors must be placed at the range start
@@ -883,7 +886,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
             }
             fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
-                A, S, a, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
+                A, S, a, sa, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
             if (A.mode != kModeFill && threadIdx.x == 0) {
                 A.task_cnt[t] = (int32_t)produced;
                 my_pairs += produced;

@@ -79,17 +79,18 @@ hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t
 hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
                                     int32_t *dst);
 
-// Filtered membership lists N_s(v): the items of v's list with size >= s.
+// Filtered membership lists N_s(v): the items b of v's list with size >=
+// s (s_item[b] when s_item is given: every item carries its own s).
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         const int32_t *ptrI, int32_t s, const int32_t *ptrS, int32_t *cntS,
-                         int32_t *itmS);
+                         const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
+                         int32_t *cntS, int32_t *itmS);
 
 // Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
 // in N_s(v) for member incidence k of a kept item a) and the run totals:
 // totals[0] = kept items, [1] = kept incidences, [2] = wedges.
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                       int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
-                       int32_t *start, int64_t *totals);
+                       int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
+                       int64_t *cost, int32_t *start, int64_t *totals);
 
 // Lookup-only members (insertion cutoff, s > 1): a candidate b with
 // |S_a & S_b| >= s lies in at least s of the lists N_s(v), v in S_a, so if up
@@ -100,8 +101,10 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
 // cost max(W_a - flagged wedges, W_a / 3).
 constexpr int32_t kStartMask = 0x7fffffff;
 constexpr int32_t kMaxLookup = 15;  // lookup-only members per item at most
+// s_item (nullable) gives each item its own s (batches); s_max is the largest.
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                              int32_t s, const int32_t *ptrS, int32_t *start, int64_t *cost);
+                              int32_t s, const int32_t *s_item, int32_t s_max,
+                              const int32_t *ptrS, int32_t *start, int64_t *cost);
 
 // Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
 // candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is
@@ -134,6 +137,7 @@ struct CountArgs {
     const int32_t *ptrI, *memI;  // item lists
     const int32_t *ptrS, *itmS;  // filtered membership lists
     int32_t N, s;
+    const int32_t *s_item;       // per-item s (batches), or null: s for every item
     const int64_t *cost;         // W_a per item
     const int32_t *start;        // back-pointers per item incidence (see launch_cost)
     const int32_t *task_item, *task_part;
@@ -164,6 +168,37 @@ struct CountArgs {
 };
 // `mid` (may be null) is recorded between the one-wave kernel and the task kernel.
 hipError_t launch_count(hipStream_t st, const CountArgs &a, hipEvent_t mid = nullptr);
+
+// ---------------------------------------------------------------- batches
+// One graph of a batch (a device array of these drives the batch kernels).
+struct BatchGraph {
+    const int32_t *rp, *col;  // the caller's CSR
+    int32_t m, n;             // edges, vertices
+    int32_t dual, s;
+    int64_t nnz;              // row_ptr[m]: every row must lie inside [0, nnz)
+    int64_t ibase, mbase;     // first combined item id, first combined member id
+    int64_t dbase, dzbase;    // dual graphs: first row and first entry in XD
+    int64_t vdbase;           // dual graphs: first row of XD^T (vertex rows)
+};
+
+hipError_t launch_batch_nnz(hipStream_t st, const BatchGraph *gr, int32_t G, int64_t *nnz,
+                            int32_t *err);
+// XD = rows of the GD dual graphs (graph dual_ids[q] has rows [dbase[q], dbase[q+1])).
+hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32_t *dual_ids,
+                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xrp,
+                               int32_t *xcol, int32_t *xrow, int32_t *err);
+// Combined items: graph g owns [ibase[g], ibase[g + 1]); ptrT / colT = XD^T.
+hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
+                            int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
+                            int32_t *err);
+hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
+                             int64_t NI, const int32_t *ptrT, const int32_t *colT,
+                             const int32_t *ptrC, int32_t *memC, int32_t *err);
+hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, const int32_t *a,
+                               int64_t P, int64_t *off);
+hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,
+                              const int32_t *a, const int32_t *b, const int32_t *w, int64_t P,
+                              int32_t *const *oa, int32_t *const *ob, int32_t *const *ow);
 
 // Copy staged ranges to their final place (skipping tasks flagged in need).
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);

@@ -306,11 +306,12 @@ __global__ void k_bitonic_step(int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
 // -------------------------------------------------------- s filtering
 
 // One wave per member list (grid-stride).  Pass 1 (itmS == nullptr) counts
-// the items of size >= s; pass 2 writes them, in list order, at ptrS[v].
+// the items of size >= s (s_item[b] for item b when given); pass 2 writes
+// them, in list order, at ptrS[v].
 __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32_t *itmM,
                                                 int32_t M, const int32_t *ptrI, int32_t s,
-                                                const int32_t *ptrS, int32_t *cntS,
-                                                int32_t *itmS) {
+                                                const int32_t *s_item, const int32_t *ptrS,
+                                                int32_t *cntS, int32_t *itmS) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32
             int32_t it = 0;
             if (k < e) {
                 it = itmM[k];
-                keep = (ptrI[it + 1] - ptrI[it]) >= s;
+                keep = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s);
             }
             const uint64_t bal = __ballot(keep);
             if (itmS && keep) itmS[run + lanes_below(bal)] = it;
@@ -338,16 +339,16 @@ __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32
 // incidence k of a kept item, start[k] = index in itmS of the first item > a
 // in N_s(v) (the back-pointer where a's walk over v begins).
 __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t *memI,
-                                              int32_t N, int32_t s, const int32_t *ptrS,
-                                              const int32_t *itmS, int64_t *cost,
-                                              int32_t *start, int64_t *totals) {
+                                              int32_t N, int32_t s, const int32_t *s_item,
+                                              const int32_t *ptrS, const int32_t *itmS,
+                                              int64_t *cost, int32_t *start, int64_t *totals) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     int64_t kept = 0, kept_nnz = 0, wedges = 0;
     for (int64_t a = wave; a < N; a += nwaves) {
         const int32_t b = ptrI[a], e = ptrI[a + 1];
-        if (e - b < s) {
+        if (e - b < (s_item ? s_item[a] : s)) {
             if (lane == 0) cost[a] = 0;
             continue;
         }
@@ -379,13 +380,15 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
 // its inserting members (they fill the table), but at least a third of W_a
 // (every wedge is still read).
 __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const int32_t *memI,
-                                                     int32_t N, int32_t s, const int32_t *ptrS,
+                                                     int32_t N, int32_t s_all,
+                                                     const int32_t *s_item, const int32_t *ptrS,
                                                      int32_t *start, int64_t *cost) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t a = wave; a < N; a += nwaves) {
         const int32_t b = ptrI[a], e = ptrI[a + 1];
+        const int32_t s = s_item ? s_item[a] : s_all;
         if (e - b < s) continue;
         const int32_t rounds = min(min(s - 1, kMaxLookup), e - b - 1);
         int64_t flagged = 0;
@@ -529,28 +532,29 @@ hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t 
 }
 
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         const int32_t *ptrI, int32_t s, const int32_t *ptrS, int32_t *cntS,
-                         int32_t *itmS) {
+                         const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
+                         int32_t *cntS, int32_t *itmS) {
     if (M <= 0) return hipSuccess;
     k_filter<<<grid_for((int64_t)M * kWave, 256, 65536), 256, 0, st>>>(ptrM, itmM, M, ptrI, s,
-                                                                       ptrS, cntS, itmS);
+                                                                       s_item, ptrS, cntS, itmS);
     return hipGetLastError();
 }
 
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                       int32_t s, const int32_t *ptrS, const int32_t *itmS, int64_t *cost,
-                       int32_t *start, int64_t *totals) {
+                       int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
+                       int64_t *cost, int32_t *start, int64_t *totals) {
     if (N <= 0) return hipSuccess;
-    k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s, ptrS,
-                                                                     itmS, cost, start, totals);
+    k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(
+        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals);
     return hipGetLastError();
 }
 
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
-                              int32_t s, const int32_t *ptrS, int32_t *start, int64_t *cost) {
-    if (N <= 0 || s <= 1) return hipSuccess;
-    k_mark_lookup<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(ptrI, memI, N, s,
-                                                                           ptrS, start, cost);
+                              int32_t s, const int32_t *s_item, int32_t s_max,
+                              const int32_t *ptrS, int32_t *start, int64_t *cost) {
+    if (N <= 0 || s_max <= 1) return hipSuccess;
+    k_mark_lookup<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(
+        ptrI, memI, N, s, s_item, ptrS, start, cost);
     return hipGetLastError();
 }
 

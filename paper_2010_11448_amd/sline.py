@@ -86,6 +86,10 @@ SIGNATURES = {
     "sline_destroy": (None, [ctypes.c_void_p]),
     "sline_build": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
+    "sline_build_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sline_csr),
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
+                                           ctypes.POINTER(sline_edges)]),
     "sline_edges_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
     "sline_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_stats)]),
     "sline_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
@@ -134,6 +138,15 @@ def sline_destroy(ctx) -> None:
 
 def sline_build(ctx, csr: sline_csr, s: int, dual: int, flags: int, out: sline_edges) -> int:
     return load().sline_build(ctx, csr, s, dual, flags, ctypes.byref(out))
+
+
+def sline_build_batch(ctx, csrs, s, dual, flags: int, outs) -> int:
+    """csrs: sequence of sline_csr; s, dual: int sequences; outs: ctypes array of sline_edges."""
+    G = len(csrs)
+    carr = (sline_csr * G)(*csrs)
+    sarr = (ctypes.c_int32 * G)(*[int(x) for x in s])
+    darr = (ctypes.c_int32 * G)(*[int(x) for x in dual])
+    return load().sline_build_batch(ctx, G, carr, sarr, darr, flags, outs)
 
 
 def sline_edges_free(ctx, edges: sline_edges) -> int:
@@ -254,6 +267,37 @@ class Context:
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
         return LineGraph(a, b, w)
+
+    def build_batch(self, graphs, s, dual=None, flags: int = 0) -> list[LineGraph]:
+        """L_{s[g]} of every graph (row_ptr, col, n_vertices) in one batched call."""
+        import torch
+        G = len(graphs)
+        dual = [0] * G if dual is None else list(dual)
+        csrs = [self.csr(rp, col, n) for rp, col, n in graphs]
+        dev = torch.device("cuda", self.device)
+        probe = torch.empty((3, max(G, 1)), dtype=torch.int32, device=dev)
+        outs = (sline_edges * max(G, 1))()
+        for g in range(G):
+            outs[g] = sline_edges(0, 1, probe[0, g:].data_ptr(), probe[1, g:].data_ptr(),
+                                  probe[2, g:].data_ptr())
+        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        if st == SLINE_OK:
+            return [LineGraph(probe[0, g:g + int(outs[g].n_pairs)].clone(),
+                              probe[1, g:g + int(outs[g].n_pairs)].clone(),
+                              probe[2, g:g + int(outs[g].n_pairs)].clone()) for g in range(G)]
+        if st != SLINE_ECAPACITY:
+            raise SlineError(st, sline_last_error(self.ctx))
+        need = [int(outs[g].n_pairs) for g in range(G)]
+        bufs = []
+        for g in range(G):
+            t = torch.empty((3, max(need[g], 1)), dtype=torch.int32, device=dev)
+            bufs.append(t)
+            outs[g] = sline_edges(0, max(need[g], 1), t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr())
+        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return [LineGraph(bufs[g][0, :need[g]], bufs[g][1, :need[g]], bufs[g][2, :need[g]])
+                for g in range(G)]
 
     def stats(self) -> dict:
         return sline_last_stats(self.ctx).as_dict()
