@@ -17,6 +17,9 @@ committed rocprofv3 counter summary of that kernel when the kernel source is
 unchanged since it was taken (else null).
 
 Other forms (--form): ``dual`` (the same graph's dual, s in {2, 8, 32});
+``batch`` (512 graphs of the batched-workload law, each with its own s: one
+sline_build_batch call per step against one sline_build call per graph, same
+graphs, same GPU; --autotune first tunes the launch parameters on the batch);
 ``copy`` (a plain device copy of known size, the calibration run for the
 FETCH_SIZE / WRITE_SIZE counters).
 """
@@ -44,7 +47,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--form", default="plain", choices=["plain", "dual", "copy"])
+    p.add_argument("--form", default="plain", choices=["plain", "dual", "batch", "copy"])
+    p.add_argument("--graphs", type=int, default=512, help="batch form: number of graphs")
+    p.add_argument("--autotune", action="store_true", help="batch form: tune launch parameters first")
+    p.add_argument("--tune-budget", type=float, default=90.0)
     p.add_argument("--s", default=None, help="comma-separated s values")
     p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -136,6 +142,82 @@ def copy_calibration(steps):
                       "ms": dt * 1e3, "GBps": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+def bench_batch(args, ctx, dev):
+    """Batched form: one sline_build_batch call vs one sline_build call per graph."""
+    import torch
+
+    from paper_2010_11448_amd import autotune, gen, sline
+
+    print(f"bench: generating {args.graphs} batch graphs", file=sys.stderr, flush=True)
+    items = gen.batch_workload(args.graphs)
+    graphs = [(torch.from_numpy(it.graph.row_ptr).to(dev), torch.from_numpy(it.graph.col).to(dev),
+               it.graph.n_vertices) for it in items]
+    s_list = [it.s for it in items]
+    dual = [it.dual for it in items]
+    nnz = sum(it.graph.nnz for it in items)
+    flags = sline.SLINE_PROFILE
+
+    def run_batch():
+        res = ctx.build_batch(graphs, s_list, dual, flags)
+        del res
+
+    def run_plain():
+        for (rp, col, nv), s, d in zip(graphs, s_list, dual):
+            L = ctx.build(rp, col, nv, s, d, flags)
+            del L
+
+    tuned = None
+    if args.autotune:
+        print("bench: autotuning on the batch", file=sys.stderr, flush=True)
+        tuned, _ = autotune.tune(ctx, run_batch, budget_s=args.tune_budget,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+    for _ in range(max(args.warmup, 1)):
+        run_batch()
+        run_plain()
+    torch.cuda.synchronize()
+    tb = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        run_batch()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        print(f"bench: batch step {i + 1}/{args.steps} {tb[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    st = ctx.stats()
+    tp = []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        run_plain()
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+        print(f"bench: plain step {i + 1}/{args.steps} {tp[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    t_batch = sum(tb) / len(tb)
+    t_plain = sum(tp) / len(tp)
+    b = 12.0 * st["heavy_nnz"] + 4.0 * st["heavy_wedges"] + 8.0 * st["heavy_pairs"]
+    ach = b / 1e9 / (st["ms_tasks"] / 1e3) if st["ms_tasks"] > 0 else 0.0
+    line = {
+        "metric": "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99",
+        "value": nnz / t_batch, "unit": "incidence entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"batch_lognormal_{args.graphs}", "graphs": args.graphs, "nnz": nnz,
+                   "items": sum(it.graph.n_edges for it in items), "s": "per graph, uniform on 1..12"},
+        "batch": {"batched_entries_per_s": nnz / t_batch, "plain_entries_per_s": nnz / t_plain,
+                  "batched_vs_plain": t_plain / t_batch, "batched_p50_ms": pct([x * 1e3 for x in tb], 50),
+                  "batched_p99_ms": pct([x * 1e3 for x in tb], 99),
+                  "plain_p50_ms": pct([x * 1e3 for x in tp], 50),
+                  "plain_p99_ms": pct([x * 1e3 for x in tp], 99),
+                  "pairs": st["n_pairs"], "tuning": tuned or ctx.tuning(),
+                  "batched_stage_ms": {k: st[k] for k in ("ms_transpose", "ms_prepare", "ms_count",
+                                                          "ms_scan", "ms_fill", "ms_tasks")}},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_count_tasks (one launch per batched build)",
+                     "alg_bytes_per_launch": "12*nnz + 4*W + 8*P over the items it counts",
+                     "alg_bytes_mean": b, "ms_mean": st["ms_tasks"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,6 +233,11 @@ def main():
         copy_calibration(max(args.steps, 1))
         return
     dev = torch.device("cuda", 0)
+    if args.form == "batch":
+        ctx = sline.Context(0)
+        bench_batch(args, ctx, dev)
+        ctx.close()
+        return
     dual = 1 if args.form == "dual" else 0
     s_list = tuple(int(x) for x in args.s.split(",")) if args.s else (
         gen.DUAL_S if dual else gen.POWERLAW_S)

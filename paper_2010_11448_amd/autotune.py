@@ -1,0 +1,110 @@
+"""Autotuner for the launch parameters of the counting stage.
+
+The parameters (``sline_tuning``) change speed, never the result: task size
+in wedges, parts per workgroup group, the one-wave / workgroup split, the
+lane-walk threshold and the resident grid sizes.  ``tune`` measures a
+workload (any callable that runs builds on a Context) under candidate
+settings by coordinate descent -- one parameter at a time, keeping the best
+value before moving to the next -- within a time budget.  Results can be kept
+in a JSON cache keyed by a coarse workload signature, so a later run on a
+workload of the same class starts from the tuned setting.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Callable, Iterable
+
+SPACE: dict[str, list[int]] = {
+    "task_wedges": [2500, 3500, 5000, 7000, 10000, 14000],
+    "group_parts": [2, 4, 8, 16, 32],
+    "small_max_wedges": [0, 128, 256, 512],
+    "light_len": [2, 4, 8, 16],
+    "small_grid_per_cu": [4, 8, 16, 32],
+    "task_grid_per_cu": [2, 3, 4],
+}
+
+
+def signature(nnz: Iterable[int], s: Iterable[int], dual: Iterable[int]) -> str:
+    """Workload class: log2 buckets of total incidences and graph count, and
+    the share of each side and of small s."""
+    nnz = list(nnz)
+    s = list(s)
+    dual = list(dual)
+    tot = max(sum(nnz), 1)
+    g = max(len(nnz), 1)
+    small_s = sum(1 for x in s if x <= 2) / max(len(s), 1)
+    d = sum(dual) / max(len(dual), 1)
+    return f"nnz2^{int(math.log2(tot))}-g2^{int(math.log2(g))}-s12:{small_s:.1f}-dual:{d:.1f}"
+
+
+def _timed(ctx, run: Callable[[], None], reps: int) -> float:
+    import torch
+
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune(ctx, run: Callable[[], None], space: dict[str, list[int]] | None = None,
+         rounds: int = 2, reps: int = 1, budget_s: float = 60.0, log=None) -> tuple[dict, float]:
+    """Coordinate descent over ``space``; returns (best tuning dict, seconds)."""
+    space = space or SPACE
+    start = time.perf_counter()
+    best = ctx.tuning()
+    run()  # warm caches and workspaces
+    best_t = _timed(ctx, run, reps)
+    if log:
+        log(f"autotune: base {best} {best_t * 1e3:.1f} ms")
+    for _ in range(rounds):
+        improved = False
+        for key, values in space.items():
+            for v in values:
+                if time.perf_counter() - start > budget_s:
+                    ctx.set_tuning(**best)
+                    return best, best_t
+                if v == best[key]:
+                    continue
+                cand = {**best, key: v}
+                ctx.set_tuning(**cand)
+                t = _timed(ctx, run, reps)
+                if log:
+                    log(f"autotune: {key}={v} {t * 1e3:.1f} ms")
+                if t < best_t * 0.98:
+                    best, best_t, improved = cand, t, True
+            ctx.set_tuning(**best)
+        if not improved:
+            break
+    ctx.set_tuning(**best)
+    return best, best_t
+
+
+def load_cached(path: str, sig: str) -> dict | None:
+    try:
+        with open(path) as f:
+            return json.load(f).get(sig, {}).get("tuning")
+    except (OSError, ValueError):
+        return None
+
+
+def save_cached(path: str, sig: str, tuning: dict, seconds: float) -> None:
+    data = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+    data[sig] = {"tuning": tuning, "seconds": seconds}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
