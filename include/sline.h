@@ -185,6 +185,69 @@ sline_status sline_build_batch(sline_ctx *ctx, int32_t n_graphs, const sline_csr
                                const int32_t *s, const int32_t *dual, uint32_t flags,
                                sline_edges *outs);
 
+/* ------------------------------------------------------------- serving
+ * A query loop over resident hypergraphs.  Registered graphs stay where the
+ * caller keeps them (device CSR arrays that must outlive the server).
+ * Queries (graph, s, side) are queued on submit; each of the server's worker
+ * threads owns a context on its own HIP stream and, whenever idle, takes the
+ * queued queries in arrival order that fit the device-memory budget next to
+ * the batches already running, and counts them as one batched build
+ * (sline_build_batch).  Queries arriving meanwhile join the next batch, so
+ * batches of different workers overlap on the device.  A query's result is
+ * exactly the plain build of its graph, s and side. */
+typedef struct sline_server sline_server;
+
+/* Timing and outcome of one query (host steady clock, nanoseconds). */
+typedef struct {
+    int64_t n_pairs;
+    int64_t t_submit_ns;  /* sline_server_submit                            */
+    int64_t t_start_ns;   /* its batch was taken by a worker                 */
+    int64_t t_done_ns;    /* result complete on the device                   */
+    int32_t batch_size;   /* queries counted in the same batched build       */
+    int32_t status;       /* sline_status of the query                       */
+} sline_query_info;
+
+/* Start a server on `device` with `n_workers` (1..16) worker threads.
+ * hbm_budget_bytes caps the estimated device memory of the batches running
+ * at once (a single query above the cap still runs, alone); max_batch caps the
+ * queries per batch.  The estimate of a query is about 80 bytes per incidence
+ * plus 20 bytes per pair the result can hold (W_1 / s, where W_1 is the sum
+ * over members of C(degree, 2) on the query's side, at most N(N - 1) / 2). */
+sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_budget_bytes,
+                                 int32_t max_batch, int32_t n_workers);
+
+/* Register a hypergraph (device CSR as in sline_build, caller-owned) and get
+ * its id.  Reads the CSR once to size queries; SLINE_EINVAL if a member id
+ * is out of range. */
+sline_status sline_server_register(sline_server *srv, sline_csr H, int32_t *graph_id);
+
+/* Queue the query L_s of graph `graph_id` (dual as in sline_build). */
+sline_status sline_server_submit(sline_server *srv, int32_t graph_id, int32_t s, int32_t dual,
+                                 int64_t *ticket);
+
+/* SLINE_EBUSY while the query is queued or running.  Otherwise the ticket is
+ * retired: `info` (may be NULL) receives its timing, and on SLINE_OK `out`
+ * receives the result arrays (device memory owned by the server until
+ * sline_server_release; out->capacity is 0).  A query that failed returns its
+ * status; sline_server_last_error has the message.  Unknown tickets give
+ * SLINE_EINVAL. */
+sline_status sline_server_poll(sline_server *srv, int64_t ticket, sline_edges *out,
+                               sline_query_info *info);
+
+/* Free a result handed over by sline_server_poll, once no device work reads
+ * it any more, and zero the struct. */
+sline_status sline_server_release(sline_server *srv, sline_edges *out);
+
+/* Queries waiting and batches running (either pointer may be NULL). */
+sline_status sline_server_pending(sline_server *srv, int64_t *queued, int32_t *running);
+
+/* Message of the last failed batch ("" if none). */
+const char *sline_server_last_error(sline_server *srv);
+
+/* Stop the workers (queries still queued are dropped), free every result not
+ * yet released and the server.  NULL is allowed. */
+void sline_server_destroy(sline_server *srv);
+
 /* Release the arrays of a library-allocated result and zero the struct.
  * Caller-owned buffers (capacity > 0) are not touched. */
 sline_status sline_edges_free(sline_ctx *ctx, sline_edges *edges);

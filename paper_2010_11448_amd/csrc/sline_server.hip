@@ -1,0 +1,332 @@
+// Serving: a query loop over resident hypergraphs with continuous batching.
+//
+// Queries (graph, s, side) arrive at any time.  Each worker thread owns a
+// library context on its own HIP stream; whenever it is idle it takes, in
+// arrival order, the queued queries that fit the device-memory budget next
+// to the work already in flight, and runs them as one batched build.  Queries
+// that arrive while a batch runs are taken by the next idle worker, so
+// batches of different workers overlap on the device.  A query's result is
+// exactly that of a plain build of the same graph, s and side: batching only
+// shares launches between independent graphs.
+//
+// Admission estimate of a query (bytes): the pipeline's workspace, about
+// 80 bytes per incidence, plus 20 bytes per possible pair, where the pairs of
+// L_s are bounded by W_1 / s (every pair of L_s takes at least s of the W_1
+// wedges of its side, W_1 = sum over members of C(degree, 2)) and by
+// N(N - 1) / 2.  W_1 of both sides is computed when a graph is registered.
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/sline.h"
+#include "sline_internal.h"
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Graph {
+    sline_csr H{};
+    int64_t nnz = 0;
+    double w1[2] = {0, 0};  // W_1 of the primal and the dual side
+};
+
+struct Query {
+    int64_t ticket = 0;
+    int32_t graph = 0, s = 1, dual = 0;
+    int64_t est = 0;
+    sline_query_info info{};
+    sline_edges out{};
+    bool done = false;
+    int32_t worker = -1;
+};
+
+}  // namespace
+
+struct sline_server {
+    int device = 0;
+    int64_t budget = 0;
+    int32_t max_batch = 64;
+    std::vector<Graph> graphs;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int64_t> queue;                    // tickets waiting, in arrival order
+    std::unordered_map<int64_t, Query> queries;   // every ticket not yet handed over
+    int64_t next_ticket = 1;
+    int64_t in_flight = 0;                        // estimated bytes of running batches
+    int32_t running = 0;                          // batches on the device
+    bool stop = false;
+    struct Worker {
+        sline_ctx *ctx = nullptr;
+        hipStream_t stream = nullptr;
+        std::thread th;
+    };
+    std::vector<Worker> workers;
+    hipStream_t rel_stream = nullptr;             // frees handed-over results
+    std::string last_error;
+};
+
+namespace {
+
+int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual) {
+    const double N = dual ? g.H.n_vertices : g.H.n_edges;
+    const double pairs = std::min(g.w1[dual] / std::max(s, 1), N * (N - 1.0) / 2.0);
+    return (int64_t)(80.0 * (double)g.nnz + 20.0 * pairs) + (1 << 20);
+}
+
+void worker_loop(sline_server *S, int wi) {
+    sline_server::Worker &W = S->workers[wi];
+    hipSetDevice(S->device);
+    for (;;) {
+        std::vector<int64_t> batch;
+        int64_t est = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (;;) {
+                if (S->stop) return;
+                // admit in arrival order while the batch and the budget allow;
+                // a query larger than the budget runs alone when nothing else does
+                while (!S->queue.empty() && (int32_t)batch.size() < S->max_batch) {
+                    Query &q = S->queries[S->queue.front()];
+                    const bool alone = S->in_flight == 0 && batch.empty();
+                    if (!alone && S->in_flight + est + q.est > S->budget) break;
+                    est += q.est;
+                    batch.push_back(q.ticket);
+                    S->queue.pop_front();
+                }
+                if (!batch.empty()) break;
+                S->cv.wait(lk);
+            }
+            S->in_flight += est;
+            S->running += 1;
+        }
+        const int32_t G = (int32_t)batch.size();
+        std::vector<sline_csr> Hs(G);
+        std::vector<int32_t> ss(G), ds(G);
+        std::vector<sline_edges> outs(G);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            const int64_t t = now_ns();
+            for (int32_t g = 0; g < G; ++g) {
+                Query &q = S->queries[batch[g]];
+                Hs[g] = S->graphs[q.graph].H;
+                ss[g] = q.s;
+                ds[g] = q.dual;
+                outs[g] = sline_edges{};
+                q.info.t_start_ns = t;
+                q.info.batch_size = G;
+                q.worker = wi;
+            }
+        }
+        const sline_status st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), 0, outs.data());
+        const int64_t t_done = now_ns();
+        std::string err = st == SLINE_OK ? std::string() : std::string(sline_last_error(W.ctx));
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (int32_t g = 0; g < G; ++g) {
+                Query &q = S->queries[batch[g]];
+                q.info.status = st;
+                q.info.t_done_ns = t_done;
+                if (st == SLINE_OK) {
+                    q.out = outs[g];
+                    q.info.n_pairs = outs[g].n_pairs;
+                }
+                q.done = true;
+            }
+            if (st != SLINE_OK) S->last_error = err;
+            S->in_flight -= est;
+            S->running -= 1;
+        }
+        S->cv.notify_all();
+    }
+}
+
+// Results come from the workers' contexts (stream-ordered device allocator);
+// they are freed on the server's own stream so a release never waits for a
+// worker's batch.
+void free_arrays(sline_server *S, const sline_edges &e) {
+    if (e.a) (void)hipFreeAsync(e.a, S->rel_stream);
+    if (e.b) (void)hipFreeAsync(e.b, S->rel_stream);
+    if (e.w) (void)hipFreeAsync(e.w, S->rel_stream);
+    (void)hipStreamSynchronize(S->rel_stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_budget_bytes,
+                                 int32_t max_batch, int32_t n_workers) {
+    if (!srv || hbm_budget_bytes <= 0 || max_batch < 1 || n_workers < 1 || n_workers > 16)
+        return SLINE_EINVAL;
+    *srv = nullptr;
+    sline_server *S = new (std::nothrow) sline_server();
+    if (!S) return SLINE_ENOMEM;
+    S->device = device;
+    S->budget = hbm_budget_bytes;
+    S->max_batch = max_batch;
+    if (hipSetDevice(device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete S;
+        return SLINE_EDEVICE;
+    }
+    if (hipStreamCreateWithFlags(&S->rel_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete S;
+        return SLINE_EDEVICE;
+    }
+    S->workers.resize(n_workers);
+    for (auto &W : S->workers) {
+        if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            sline_server_destroy(S);
+            return SLINE_EDEVICE;
+        }
+        const sline_status st = sline_create(&W.ctx, device, W.stream, nullptr);
+        if (st != SLINE_OK) {
+            sline_server_destroy(S);
+            return st;
+        }
+    }
+    try {
+        for (int i = 0; i < n_workers; ++i) S->workers[i].th = std::thread(worker_loop, S, i);
+    } catch (...) {
+        sline_server_destroy(S);
+        return SLINE_ENOMEM;
+    }
+    *srv = S;
+    return SLINE_OK;
+}
+
+sline_status sline_server_register(sline_server *S, sline_csr H, int32_t *graph_id) {
+    if (!S || !graph_id || H.n_edges < 0 || H.n_vertices < 0 || (H.n_edges > 0 && !H.row_ptr))
+        return SLINE_EINVAL;
+    Graph g;
+    g.H = H;
+    // W_1 of both sides from the item sizes and the vertex degrees
+    std::vector<int32_t> rp((size_t)H.n_edges + 1, 0);
+    if (H.n_edges > 0 &&
+        hipMemcpy(rp.data(), H.row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return SLINE_EDEVICE;
+    }
+    g.nnz = rp.back();
+    if (g.nnz < 0 || (g.nnz > 0 && (!H.col_idx || H.n_vertices == 0))) return SLINE_EINVAL;
+    for (int32_t e = 0; e < H.n_edges; ++e) {
+        const double k = rp[e + 1] - rp[e];
+        if (k < 0) return SLINE_EINVAL;
+        g.w1[1] += k * (k - 1) / 2;
+    }
+    if (g.nnz > 0) {
+        std::vector<int32_t> col((size_t)g.nnz);
+        if (hipMemcpy(col.data(), H.col_idx, sizeof(int32_t) * col.size(), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return SLINE_EDEVICE;
+        }
+        std::vector<int32_t> deg((size_t)H.n_vertices, 0);
+        for (int32_t v : col) {
+            if (v < 0 || v >= H.n_vertices) return SLINE_EINVAL;
+            deg[v] += 1;
+        }
+        for (int32_t d : deg) g.w1[0] += (double)d * (d - 1) / 2;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    *graph_id = (int32_t)S->graphs.size();
+    S->graphs.push_back(g);
+    return SLINE_OK;
+}
+
+sline_status sline_server_submit(sline_server *S, int32_t graph_id, int32_t s, int32_t dual,
+                                 int64_t *ticket) {
+    if (!S || !ticket || s < 1 || (dual != 0 && dual != 1)) return SLINE_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (graph_id < 0 || graph_id >= (int32_t)S->graphs.size()) return SLINE_EINVAL;
+        Query q;
+        q.ticket = S->next_ticket++;
+        q.graph = graph_id;
+        q.s = s;
+        q.dual = dual;
+        q.est = estimate(S, S->graphs[graph_id], s, dual);
+        q.info.t_submit_ns = now_ns();
+        q.info.status = SLINE_EBUSY;
+        *ticket = q.ticket;
+        S->queries.emplace(q.ticket, q);
+        S->queue.push_back(q.ticket);
+    }
+    S->cv.notify_all();
+    return SLINE_OK;
+}
+
+sline_status sline_server_poll(sline_server *S, int64_t ticket, sline_edges *out,
+                               sline_query_info *info) {
+    if (!S || !out) return SLINE_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->queries.find(ticket);
+    if (it == S->queries.end()) return SLINE_EINVAL;
+    if (!it->second.done) return SLINE_EBUSY;
+    const Query q = it->second;
+    S->queries.erase(it);
+    if (info) *info = q.info;
+    if (q.info.status != SLINE_OK) return q.info.status;
+    *out = q.out;
+    out->capacity = 0;
+    // the arrays stay owned by the server until sline_server_release
+    return SLINE_OK;
+}
+
+sline_status sline_server_release(sline_server *S, sline_edges *out) {
+    if (!S || !out) return SLINE_EINVAL;
+    free_arrays(S, *out);
+    out->a = out->b = out->w = nullptr;
+    out->n_pairs = 0;
+    return SLINE_OK;
+}
+
+sline_status sline_server_pending(sline_server *S, int64_t *queued, int32_t *running) {
+    if (!S) return SLINE_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (queued) *queued = (int64_t)S->queue.size();
+    if (running) *running = S->running;
+    return SLINE_OK;
+}
+
+const char *sline_server_last_error(sline_server *S) {
+    return S ? S->last_error.c_str() : "no server";
+}
+
+void sline_server_destroy(sline_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto &W : S->workers)
+        if (W.th.joinable()) W.th.join();
+    for (auto &kv : S->queries)
+        if (kv.second.done) free_arrays(S, kv.second.out);
+    for (auto &W : S->workers) {
+        if (W.ctx) sline_destroy(W.ctx);
+        if (W.stream) (void)hipStreamDestroy(W.stream);
+    }
+    if (S->rel_stream) (void)hipStreamDestroy(S->rel_stream);
+    delete S;
+}
+
+}  // extern "C"

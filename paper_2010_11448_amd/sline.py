@@ -63,6 +63,15 @@ class sline_tuning(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class sline_query_info(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("t_submit_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -95,6 +104,20 @@ SIGNATURES = {
     "sline_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
     "sline_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
     "sline_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "sline_server_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                             ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+    "sline_server_register": (ctypes.c_int32, [ctypes.c_void_p, sline_csr,
+                                               ctypes.POINTER(ctypes.c_int32)]),
+    "sline_server_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "sline_server_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.POINTER(sline_edges),
+                                           ctypes.POINTER(sline_query_info)]),
+    "sline_server_release": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
+    "sline_server_pending": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int32)]),
+    "sline_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "sline_server_destroy": (None, [ctypes.c_void_p]),
     "sline_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
@@ -314,3 +337,83 @@ class Context:
         st = sline_set_tuning(self.ctx, t)
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
+
+
+# -------------------------------------------------------------- serving
+
+class _DeviceArray:
+    """Zero-copy view of a device int32 array for torch.as_tensor."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4", "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+class Server:
+    """A query loop over registered hypergraphs (sline_server_* of the C-ABI)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, max_batch: int = 64,
+                 workers: int = 2):
+        lib = load()
+        self.device = device
+        self.srv = ctypes.c_void_p()
+        st = lib.sline_server_create(ctypes.byref(self.srv), device, int(hbm_budget_bytes),
+                                     int(max_batch), int(workers))
+        if st != SLINE_OK:
+            raise SlineError(st, "sline_server_create failed")
+        self._keep = []
+
+    def register(self, row_ptr, col, n_vertices: int) -> int:
+        gid = ctypes.c_int32()
+        st = load().sline_server_register(self.srv, Context.csr(row_ptr, col, n_vertices),
+                                          ctypes.byref(gid))
+        if st != SLINE_OK:
+            raise SlineError(st, "sline_server_register failed")
+        self._keep.append((row_ptr, col))
+        return int(gid.value)
+
+    def submit(self, graph_id: int, s: int, dual: int = 0) -> int:
+        t = ctypes.c_int64()
+        st = load().sline_server_submit(self.srv, graph_id, s, dual, ctypes.byref(t))
+        if st != SLINE_OK:
+            raise SlineError(st, "sline_server_submit failed")
+        return int(t.value)
+
+    def pending(self) -> tuple[int, int]:
+        q, r = ctypes.c_int64(), ctypes.c_int32()
+        load().sline_server_pending(self.srv, ctypes.byref(q), ctypes.byref(r))
+        return int(q.value), int(r.value)
+
+    def poll(self, ticket: int, keep: bool = True):
+        """None while running; else (LineGraph copy or None, info dict)."""
+        import torch
+        out = sline_edges()
+        info = sline_query_info()
+        st = load().sline_server_poll(self.srv, ticket, ctypes.byref(out), ctypes.byref(info))
+        if st == SLINE_EBUSY:
+            return None
+        if st != SLINE_OK:
+            raise SlineError(st, load().sline_server_last_error(self.srv).decode())
+        n = int(out.n_pairs)
+        L = None
+        if keep:
+            dev = torch.device("cuda", self.device)
+            if n > 0:
+                L = LineGraph(*[torch.as_tensor(_DeviceArray(p, n), device=dev).clone()
+                                for p in (out.a, out.b, out.w)])
+            else:
+                L = LineGraph(*[torch.empty(0, dtype=torch.int32, device=dev) for _ in range(3)])
+            torch.cuda.synchronize(dev)
+        load().sline_server_release(self.srv, ctypes.byref(out))
+        return L, info.as_dict()
+
+    def close(self) -> None:
+        if self.srv:
+            load().sline_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,117 @@
+"""Serving (continuous batching) through the C-ABI.
+
+Bar: bit-exact -- every query answered by the server, whatever batch it ran
+in, equals the plain build of the same graph, s and side (and the oracle).
+"""
+
+from __future__ import annotations
+
+import time
+
+import pytest
+
+import oracle
+from paper_2010_11448_amd import gen
+
+from helpers import assert_same, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch.device("cuda", 0)
+
+
+def _catalog():
+    graphs = [gen.uniform_2000(11), gen.uniform_2000(12), gen.powerlaw_1m(scale=0.01),
+              gen.random_small(60, 40, 12, 7), gen.sunflower(300, 6, 5, seed=3),
+              gen.nested_chain(40, 7, seed=4)]
+    graphs += [gen.batch_graph(g, m_cap=3000).graph for g in range(6)]
+    return graphs
+
+
+def _drain(srv, tickets, timeout_s=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t in done:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                done[t] = r
+        assert time.time() - t0 < timeout_s, "server did not finish"
+        time.sleep(0.001)
+    return done
+
+
+@pytest.mark.parametrize("workers,budget", [(2, 64 << 30), (1, 1 << 20)])
+def test_mixed_queries_equal_alone(dev, workers, budget):
+    from paper_2010_11448_amd import sline
+
+    graphs = _catalog()
+    dg = [to_device(h, dev) for h in graphs]
+    srv = sline.Server(0, hbm_budget_bytes=budget, max_batch=16, workers=workers)
+    ctx = sline.Context(0)
+    try:
+        ids = [srv.register(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)]
+        st = gen.Stream(99)
+        queries = []
+        for _ in range(60):
+            g = int(st.integers(0, len(graphs) - 1, 1)[0])
+            queries.append((g, int(st.integers(1, 6, 1)[0]), int(st.integers(0, 1, 1)[0])))
+        print(f"case: serve workers={workers} budget={budget} queries={len(queries)}", flush=True)
+        tickets = [srv.submit(ids[g], s, d) for g, s, d in queries]
+        done = _drain(srv, tickets)
+        sizes = [done[t][1]["batch_size"] for t in tickets]
+        if budget >= 1 << 30:
+            assert max(sizes) > 1, "queries submitted together should share batches"
+        else:
+            # every estimate exceeds a 1 MiB budget: each query runs alone
+            assert max(sizes) == 1
+        for (g, s, d), t in zip(queries, tickets):
+            L, info = done[t]
+            assert info["status"] == 0 and info["n_pairs"] == len(L)
+            assert info["t_submit_ns"] <= info["t_start_ns"] <= info["t_done_ns"]
+            rp, col = dg[g]
+            alone = ctx.build(rp, col, graphs[g].n_vertices, s, d)
+            assert_same(L, oracle.Pairs(alone.a.cpu().numpy(), alone.b.cpu().numpy(),
+                                        alone.w.cpu().numpy()),
+                        f"graph {g} s={s} dual={d} in a batch of {info['batch_size']}")
+        # one query per graph against the oracle as well
+        for g in range(len(graphs)):
+            h = graphs[g]
+            ref, _ = oracle.wedge(h.row_ptr, h.col, h.n_edges, h.n_vertices, 2, dual=g % 2,
+                                  threads=8)
+            t = srv.submit(ids[g], 2, g % 2)
+            L, _ = _drain(srv, [t])[t]
+            assert_same(L, ref, f"served graph {g} vs oracle")
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_server_errors(dev):
+    from paper_2010_11448_amd import sline
+
+    srv = sline.Server(0, hbm_budget_bytes=1 << 30, max_batch=4, workers=1)
+    try:
+        g = gen.uniform_2000(11)
+        rp, col = to_device(g, dev)
+        gid = srv.register(rp, col, g.n_vertices)
+        for bad in ((gid, 0, 0), (gid, 1, 2), (gid + 5, 1, 0)):
+            with pytest.raises(sline.SlineError) as ei:
+                srv.submit(*bad)
+            assert ei.value.status == sline.SLINE_EINVAL
+        with pytest.raises(sline.SlineError):
+            srv.poll(12345)
+        t = srv.submit(gid, 3, 0)
+        L, info = _drain(srv, [t])[t]
+        assert info["n_pairs"] == len(L)
+        assert srv.pending() == (0, 0)
+    finally:
+        srv.close()
