@@ -20,8 +20,12 @@ Other forms (--form): ``dual`` (the same graph's dual, s in {2, 8, 32});
 ``batch`` (512 graphs of the batched-workload law, each with its own s: one
 sline_build_batch call per step against one sline_build call per graph, same
 graphs, same GPU; --autotune first tunes the launch parameters on the batch);
-``copy`` (a plain device copy of known size, the calibration run for the
-FETCH_SIZE / WRITE_SIZE counters).
+``serve`` (a catalog of batch-law graphs plus power-law graphs of the
+1,000,000 x 2,000,000 size, queried by Poisson arrivals at 200/s with s on
+1..16 and a random side through the serving loop: p50/p99 latency from
+submit to result on the device, throughput, and the same queries run back to
+back with one plain call each); ``copy`` (a plain device copy of known size,
+the calibration run for the FETCH_SIZE / WRITE_SIZE counters).
 """
 
 from __future__ import annotations
@@ -47,7 +51,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--form", default="plain", choices=["plain", "dual", "batch", "copy"])
+    p.add_argument("--form", default="plain", choices=["plain", "dual", "batch", "serve", "copy"])
+    p.add_argument("--duration", type=float, default=20.0, help="serve form: seconds of arrivals")
+    p.add_argument("--rate", type=float, default=200.0, help="serve form: arrivals per second")
+    p.add_argument("--catalog-small", type=int, default=256)
+    p.add_argument("--catalog-large", type=int, default=2)
+    p.add_argument("--budget-gb", type=float, default=160.0)
+    p.add_argument("--workers", type=int, default=2)
     p.add_argument("--graphs", type=int, default=512, help="batch form: number of graphs")
     p.add_argument("--autotune", action="store_true", help="batch form: tune launch parameters first")
     p.add_argument("--tune-budget", type=float, default=90.0)
@@ -218,6 +228,107 @@ def bench_batch(args, ctx, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args, dev):
+    """Serving form: Poisson arrivals through the query loop, then the same
+    queries with one plain call each."""
+    import torch
+
+    from paper_2010_11448_amd import gen, sline
+
+    print("bench: generating the serving catalog", file=sys.stderr, flush=True)
+    cat = [gen.batch_graph(g).graph for g in range(args.catalog_small)]
+    cat += [gen.powerlaw_1m(seed=21 + i) for i in range(args.catalog_large)]
+    dgr = [(torch.from_numpy(h.row_ptr).to(dev), torch.from_numpy(h.col).to(dev), h.n_vertices)
+           for h in cat]
+    qs = gen.serving_arrivals(args.catalog_small, args.catalog_large, rate=args.rate,
+                              duration_s=args.duration)
+    srv = sline.Server(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=64,
+                       workers=args.workers)
+    ids = [srv.register(rp, col, n) for rp, col, n in dgr]
+    # warm the server: a few queries, and the largest result of each large
+    # graph (maps the device memory its cache will reuse)
+    warm = [(ids[q.graph_id], q.s, q.dual) for q in qs[:8]]
+    warm += [(ids[args.catalog_small + i], 1, 0) for i in range(args.catalog_large)]
+    for gid, s_, d_ in warm:
+        t = srv.submit(gid, s_, d_)
+        while srv.poll(t, keep=False) is None:
+            time.sleep(0.0005)
+    print(f"bench: serving {len(qs)} queries over {args.duration:.0f} s", file=sys.stderr, flush=True)
+    infos = {}
+    outstanding = []
+    t0 = time.perf_counter()
+    k = 0
+    last_print = t0
+    while k < len(qs) or outstanding:
+        now = time.perf_counter() - t0
+        while k < len(qs) and qs[k].arrival_s <= now:
+            q = qs[k]
+            outstanding.append((srv.submit(ids[q.graph_id], q.s, q.dual), k))
+            k += 1
+        still = []
+        for t, i in outstanding:
+            r = srv.poll(t, keep=False)
+            if r is None:
+                still.append((t, i))
+            else:
+                infos[i] = r[1]
+        outstanding = still
+        if time.perf_counter() - last_print > 5.0:
+            last_print = time.perf_counter()
+            qd, rn = srv.pending()
+            print(f"bench: served {len(infos)}/{len(qs)} (submitted {k}, queued {qd}, "
+                  f"running batches {rn})", file=sys.stderr, flush=True)
+        if k < len(qs):
+            time.sleep(max(0.0, min(0.0005, qs[k].arrival_s - (time.perf_counter() - t0))))
+        else:
+            time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    lat = [(infos[i]["t_done_ns"] - infos[i]["t_submit_ns"]) / 1e6 for i in range(len(qs))]
+    nnz = sum(cat[q.graph_id].nnz for q in qs)
+    batch_sizes = [infos[i]["batch_size"] for i in range(len(qs))]
+    first = min(infos[i]["t_submit_ns"] for i in range(len(qs)))
+    last = max(infos[i]["t_done_ns"] for i in range(len(qs)))
+    # saturation: every query submitted at once
+    t1 = time.perf_counter()
+    ts = [srv.submit(ids[q.graph_id], q.s, q.dual) for q in qs]
+    for t in ts:
+        while srv.poll(t, keep=False) is None:
+            time.sleep(0.0002)
+    t_sat = time.perf_counter() - t1
+    srv.close()
+    print("bench: plain calls, one per query", file=sys.stderr, flush=True)
+    ctx = sline.Context(0)
+    t2 = time.perf_counter()
+    for q in qs:
+        rp, col, n = dgr[q.graph_id]
+        L = ctx.build(rp, col, n, q.s, q.dual)
+        del L
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t2
+    ctx.close()
+    large = [lat[i] for i, q in enumerate(qs) if q.graph_id >= args.catalog_small]
+    line = {
+        "metric": "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99",
+        "value": nnz / t_sat, "unit": "incidence entries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_sat * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"serving_poisson{args.rate:.0f}_{args.duration:.0f}s",
+                   "queries": len(qs), "catalog_small": args.catalog_small,
+                   "catalog_large": args.catalog_large, "budget_gb": args.budget_gb,
+                   "workers": args.workers},
+        "serve": {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
+                  "large_p50_ms": pct(large, 50), "large_p99_ms": pct(large, 99),
+                  "queries_per_s_arrival_run": len(qs) / ((last - first) / 1e9),
+                  "entries_per_s_arrival_run": nnz / ((last - first) / 1e9),
+                  "wall_s": wall, "mean_batch": sum(batch_sizes) / len(batch_sizes),
+                  "max_batch": max(batch_sizes),
+                  "saturation_s": t_sat, "saturation_queries_per_s": len(qs) / t_sat,
+                  "plain_s": t_plain, "plain_queries_per_s": len(qs) / t_plain,
+                  "served_vs_plain": t_plain / t_sat},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,6 +348,9 @@ def main():
         ctx = sline.Context(0)
         bench_batch(args, ctx, dev)
         ctx.close()
+        return
+    if args.form == "serve":
+        bench_serve(args, dev)
         return
     dual = 1 if args.form == "dual" else 0
     s_list = tuple(int(x) for x in args.s.split(",")) if args.s else (

@@ -736,6 +736,15 @@ sline_status batch_split(sline_ctx *c, int32_t G, sline_edges *outs) {
             return SLINE_ECAPACITY;
         }
     }
+    if (G == 1 && outs[0].capacity == 0) {
+        // one graph: its items start at id 0, so the combined arrays are its result
+        outs[0].n_pairs = P.comb.n_pairs;
+        outs[0].a = P.comb.a;
+        outs[0].b = P.comb.b;
+        outs[0].w = P.comb.w;
+        P.comb = sline_edges{};
+        return SLINE_OK;
+    }
     std::vector<int32_t *> pa(G), pb(G), pw(G);
     std::vector<char> owned(G, 0);
     try {

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -44,6 +45,82 @@ struct Graph {
     int64_t nnz = 0;
     double w1[2] = {0, 0};  // W_1 of the primal and the dual side
 };
+
+// Device memory cache shared by the workers (and the release of handed-over
+// results): freed blocks are kept and reused for requests up to 1.5x smaller,
+// so the large result and staging arrays of a serving loop are mapped once.
+// When hipMalloc fails the cache is emptied and the request retried.
+struct DeviceCache {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;   // size -> block
+    std::map<void *, size_t> sizes;              // every live or cached block
+
+    static size_t round(size_t n) {
+        const size_t g = (size_t)2 << 20;
+        return (std::max<size_t>(n, 1) + g - 1) & ~(g - 1);
+    }
+
+    void *alloc(size_t n) {
+        n = round(n);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = free_blocks.lower_bound(n);
+            if (it != free_blocks.end() && it->first <= n + n / 2 + ((size_t)2 << 20)) {
+                void *p = it->second;
+                free_blocks.erase(it);
+                return p;
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&p, n) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        sizes[p] = n;
+        return p;
+    }
+
+    void release(void *p, hipStream_t st) {
+        if (!p) return;
+        // the block may next serve another stream: let this one finish with it
+        if (st) (void)hipStreamSynchronize(st);
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = sizes.find(p);
+        if (it == sizes.end()) return;
+        free_blocks.emplace(it->second, p);
+    }
+
+    void trim() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : free_blocks) {
+            (void)hipFree(kv.second);
+            sizes.erase(kv.second);
+        }
+        free_blocks.clear();
+    }
+
+    void destroy() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : sizes) (void)hipFree(kv.first);
+        sizes.clear();
+        free_blocks.clear();
+    }
+};
+
+void *cache_alloc(size_t n, void *stream, void *user) {
+    (void)stream;
+    return static_cast<DeviceCache *>(user)->alloc(n);
+}
+
+void cache_free(void *p, size_t n, void *stream, void *user) {
+    (void)n;
+    static_cast<DeviceCache *>(user)->release(p, static_cast<hipStream_t>(stream));
+}
 
 struct Query {
     int64_t ticket = 0;
@@ -76,7 +153,7 @@ struct sline_server {
         std::thread th;
     };
     std::vector<Worker> workers;
-    hipStream_t rel_stream = nullptr;             // frees handed-over results
+    DeviceCache cache;                            // device memory of every worker
     std::string last_error;
 };
 
@@ -155,14 +232,11 @@ void worker_loop(sline_server *S, int wi) {
     }
 }
 
-// Results come from the workers' contexts (stream-ordered device allocator);
-// they are freed on the server's own stream so a release never waits for a
-// worker's batch.
+// Results live in the server's cache; a release returns them to it.
 void free_arrays(sline_server *S, const sline_edges &e) {
-    if (e.a) (void)hipFreeAsync(e.a, S->rel_stream);
-    if (e.b) (void)hipFreeAsync(e.b, S->rel_stream);
-    if (e.w) (void)hipFreeAsync(e.w, S->rel_stream);
-    (void)hipStreamSynchronize(S->rel_stream);
+    S->cache.release(e.a, nullptr);
+    S->cache.release(e.b, nullptr);
+    S->cache.release(e.w, nullptr);
 }
 
 }  // namespace
@@ -184,11 +258,10 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
         delete S;
         return SLINE_EDEVICE;
     }
-    if (hipStreamCreateWithFlags(&S->rel_stream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        delete S;
-        return SLINE_EDEVICE;
-    }
+    sline_allocator al{};
+    al.alloc = cache_alloc;
+    al.free = cache_free;
+    al.user = &S->cache;
     S->workers.resize(n_workers);
     for (auto &W : S->workers) {
         if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
@@ -196,7 +269,7 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
             sline_server_destroy(S);
             return SLINE_EDEVICE;
         }
-        const sline_status st = sline_create(&W.ctx, device, W.stream, nullptr);
+        const sline_status st = sline_create(&W.ctx, device, W.stream, &al);
         if (st != SLINE_OK) {
             sline_server_destroy(S);
             return st;
@@ -325,7 +398,8 @@ void sline_server_destroy(sline_server *S) {
         if (W.ctx) sline_destroy(W.ctx);
         if (W.stream) (void)hipStreamDestroy(W.stream);
     }
-    if (S->rel_stream) (void)hipStreamDestroy(S->rel_stream);
+    (void)hipDeviceSynchronize();
+    S->cache.destroy();
     delete S;
 }
 
