@@ -194,7 +194,11 @@ sline_status sline_build_batch(sline_ctx *ctx, int32_t n_graphs, const sline_csr
  * the batches already running, and counts them as one batched build
  * (sline_build_batch).  Queries arriving meanwhile join the next batch, so
  * batches of different workers overlap on the device.  A query's result is
- * exactly the plain build of its graph, s and side. */
+ * exactly the plain build of its graph, s and side.  The workers' device
+ * memory comes from the server's own allocator: chunks of at least 4 GiB from
+ * hipMalloc, carved by best fit and kept until the server is destroyed (chunks
+ * with nothing allocated are returned when hipMalloc fails).  Setting the
+ * environment variable SLINE_SERVER_LOG prints one line per batch to stderr. */
 typedef struct sline_server sline_server;
 
 /* Timing and outcome of one query (host steady clock, nanoseconds). */

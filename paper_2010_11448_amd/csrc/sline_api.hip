@@ -415,6 +415,7 @@ void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
 // the device), between s_min and s_max.  Null for a plain build.
 struct ItemS {
     const int32_t *s_item = nullptr;
+    const int32_t *item_end = nullptr;  // one past the last item of each item's graph
     int32_t s_min = 1, s_max = 1;
 };
 
@@ -604,6 +605,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.N = (int32_t)N;
     C.s = s;
     C.s_item = IS.s_item;
+    C.item_end = IS.item_end;
     C.cost = L.cost;
     C.start = L.start;
     C.task_item = TL.item;
@@ -933,7 +935,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     // 3. XD and its transpose; 4. combined item CSR
     Arena sz;
     auto plan = [&](Arena &A, Layout &X, int32_t *&xrp, int32_t *&len, int32_t *&ptrC,
-                    int32_t *&memC, int32_t *&s_item) {
+                    int32_t *&memC, int32_t *&s_item, int32_t *&iend) {
         xrp = A.take<int32_t>(E + 1);
         X.rowid = A.take<int32_t>(ZD);
         X.colT = A.take<int32_t>(ZD);
@@ -948,11 +950,12 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         ptrC = A.take<int32_t>(NI + 1);
         memC = A.take<int32_t>(ZT);
         s_item = A.take<int32_t>(NI);
+        iend = A.take<int32_t>(NI);
         X.cntS = A.take<int32_t>(ZD);  // XD columns
     };
     Layout X{};
-    int32_t *xrp, *len, *ptrC, *memC, *s_item;
-    plan(sz, X, xrp, len, ptrC, memC, s_item);
+    int32_t *xrp, *len, *ptrC, *memC, *s_item, *iend;
+    plan(sz, X, xrp, len, ptrC, memC, s_item, iend);
     void *big = dev_alloc(c, sz.off + 4096);
     if (!big) {
         set_err(c, "batch arrays allocation failed");
@@ -964,7 +967,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     try {
         Arena A;
         A.base = reinterpret_cast<char *>(big);
-        plan(A, X, xrp, len, ptrC, memC, s_item);
+        plan(A, X, xrp, len, ptrC, memC, s_item, iend);
         int32_t *xcol = X.cntS;
         hip_check(c, launch_fill_i32(st, xcol, ZD, 0), "zero dual columns");
         hip_check(c, launch_fill_i32(st, X.rowid, ZD, 0), "zero dual rows");
@@ -978,7 +981,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         } else if (VD > 0) {
             hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
         }
-        hip_check(c, launch_batch_len(st, d_gr, P.ibase_dev, G, NI, X.ptrT, len, s_item, d_err),
+        hip_check(c, launch_batch_len(st, d_gr, P.ibase_dev, G, NI, X.ptrT, len, s_item, iend, d_err),
                   "item lengths");
         hip_check(c, launch_scan_i32(st, len, NI, ptrC, X.part32), "item scan");
         hip_check(c, launch_batch_rows(st, d_gr, P.ibase_dev, G, NI, X.ptrT, X.colT, ptrC, memC, d_err),
@@ -1000,6 +1003,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         CH.n_vertices = (int32_t)std::max<int64_t>(MT, 1);
         ItemS IS;
         IS.s_item = s_item;
+        IS.item_end = iend;
         IS.s_min = s_min;
         IS.s_max = s_max;
         const sline_status r =

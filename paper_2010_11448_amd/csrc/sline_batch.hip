@@ -89,9 +89,11 @@ __global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, cons
     }
 }
 
-// One thread per combined item: its row length and its graph's s.
+// One thread per combined item: its row length, its graph's s and the end of
+// its graph's items (candidates of an item never lie beyond it).
 __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t G, int64_t NI,
-                            const int32_t *ptrT, int32_t *len, int32_t *s_item, int32_t *err) {
+                            const int32_t *ptrT, int32_t *len, int32_t *s_item, int32_t *item_end,
+                            int32_t *err) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t g = find_graph(ibase, G, i);
@@ -111,6 +113,7 @@ __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t 
         }
         len[i] = l;
         s_item[i] = d.s;
+        item_end[i] = (int32_t)ibase[g + 1];
     }
 }
 
@@ -202,9 +205,10 @@ hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32
 
 hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                             int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
-                            int32_t *err) {
+                            int32_t *item_end, int32_t *err) {
     if (NI <= 0) return hipSuccess;
-    k_batch_len<<<grid_for(NI, 256, 65536), 256, 0, st>>>(gr, ibase, G, NI, ptrT, len, s_item, err);
+    k_batch_len<<<grid_for(NI, 256, 65536), 256, 0, st>>>(gr, ibase, G, NI, ptrT, len, s_item,
+                                                          item_end, err);
     return hipGetLastError();
 }
 

@@ -329,10 +329,10 @@ template <int NT, int RUNCAP>
 __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, const Range &R,
                                              int32_t k0, int32_t k1, const int32_t (&cur)[kR],
                                              const int32_t (&end)[kR], uint32_t lookm, bool look,
-                                             int32_t (&nc)[kR]) {
+                                             int32_t nend, int32_t (&nc)[kR]) {
     constexpr int W = NT / kWave;
     const int lane = lane_id(), wid = threadIdx.x / kWave;
-    const float frac = (float)R.span / (float)((int64_t)A.N - R.lo);
+    const float frac = (float)R.span / (float)((int64_t)nend - R.lo);
     const float light_len = (float)A.tune.light_len;
     bool ok = true;
     uint32_t light = 0;  // bit i: member i is walked by this lane
@@ -673,8 +673,8 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
 // pairs produced (block-uniform).
 template <int NT, int PAD, int RUNCAP>
 __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, int32_t a,
-                                             int32_t sa, int32_t t, int32_t lo, int32_t hi,
-                                             int32_t slots,
+                                             int32_t sa, int32_t nend, int32_t t, int32_t lo,
+                                             int32_t hi, int32_t slots,
                                              int32_t cb, int32_t k0, int32_t k1, int32_t (&cur)[kR],
                                              const int32_t (&end)[kR], uint32_t lookm,
                                              int64_t &passes) {
@@ -701,7 +701,7 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
         bool split = too_wide(R);
         if (!split) {
             int32_t nc[kR];
-            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, false, nc);
+            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, false, nend, nc);
             ++passes;
             split = S.misc[kMiscOverflow] != 0;
             if (!split && sa > 1) {
@@ -709,7 +709,7 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
                 __syncthreads();
                 if (threadIdx.x == 0) S.misc[kMiscRuns] = 0;
                 __syncthreads();
-                insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nc);
+                insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nend, nc);
             }
             if (!split) {
                 produced += tab_extract<NT>(A, S, R, a, sa, t, produced);
@@ -814,10 +814,11 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         int32_t cur[kR], end[kR];
         uint32_t lookm;
+        const int32_t nend = A.item_end ? A.item_end[a] : A.N;
         init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end, lookm);
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
-            A, S, a, A.s_item ? A.s_item[a] : A.s, t, a + 1, A.N, want, count_bits(k1 - k0), k0,
-            k1, cur, end, lookm, passes);
+            A, S, a, A.s_item ? A.s_item[a] : A.s, nend, t, a + 1, nend, want, count_bits(k1 - k0),
+            k0, k1, cur, end, lookm, passes);
         if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
     }
@@ -862,12 +863,13 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
         const int32_t sa = A.s_item ? A.s_item[a] : A.s;
+        const int32_t nend = A.item_end ? A.item_end[a] : A.N;
         int32_t cur[kR], end[kR];
         uint32_t lookm = 0;
         bool fresh = true;  // cursors must be placed at the range start
         for (int32_t q = p0; q < p1; ++q) {
             int32_t lo, hi;
-            task_range(a, A.N, q, P, lo, hi);
+            task_range(a, nend, q, P, lo, hi);
             const int32_t t = t0 + (q - p0);
             if (A.mode == kModeFill && A.need && !A.need[t]) {
                 fresh = true;
@@ -886,7 +888,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
             }
             fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
-                A, S, a, sa, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
+                A, S, a, sa, nend, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
             if (A.mode != kModeFill && threadIdx.x == 0) {
                 A.task_cnt[t] = (int32_t)produced;
                 my_pairs += produced;

@@ -138,6 +138,7 @@ struct CountArgs {
     const int32_t *ptrS, *itmS;  // filtered membership lists
     int32_t N, s;
     const int32_t *s_item;       // per-item s (batches), or null: s for every item
+    const int32_t *item_end;     // per item: one past the last item of its graph (batches), or null: N
     const int64_t *cost;         // W_a per item
     const int32_t *start;        // back-pointers per item incidence (see launch_cost)
     const int32_t *task_item, *task_part;
@@ -190,7 +191,7 @@ hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32
 // Combined items: graph g owns [ibase[g], ibase[g + 1]); ptrT / colT = XD^T.
 hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                             int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
-                            int32_t *err);
+                            int32_t *item_end, int32_t *err);
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                              int64_t NI, const int32_t *ptrT, const int32_t *colT,
                              const int32_t *ptrC, int32_t *memC, int32_t *err);

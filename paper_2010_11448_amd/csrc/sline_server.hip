@@ -15,6 +15,8 @@
 // wedges of its side, W_1 = sum over members of C(degree, 2)) and by
 // N(N - 1) / 2.  W_1 of both sides is computed when a graph is registered.
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -46,43 +48,67 @@ struct Graph {
     double w1[2] = {0, 0};  // W_1 of the primal and the dual side
 };
 
-// Device memory cache shared by the workers (and the release of handed-over
-// results): freed blocks are kept and reused for requests up to 1.5x smaller,
-// so the large result and staging arrays of a serving loop are mapped once.
-// When hipMalloc fails the cache is emptied and the request retried.
+// Device memory of the workers (and of handed-over results): large chunks
+// from hipMalloc, carved into blocks by best fit and merged again on release,
+// so the serving loop maps device memory once instead of per query (mapping
+// fresh memory costs more than most builds).  When no chunk has room and
+// hipMalloc fails, chunks with nothing allocated are returned and the request
+// is retried.
 struct DeviceCache {
+    struct Chunk {
+        char *base = nullptr;
+        size_t size = 0, used = 0;
+        std::map<size_t, size_t> free;  // offset -> length, merged
+    };
     std::mutex mu;
-    std::multimap<size_t, void *> free_blocks;   // size -> block
-    std::map<void *, size_t> sizes;              // every live or cached block
+    std::vector<Chunk *> chunks;
+    std::map<void *, std::pair<Chunk *, size_t>> live;  // block -> (chunk, length)
+    size_t chunk_min = (size_t)4 << 30;
 
     static size_t round(size_t n) {
         const size_t g = (size_t)2 << 20;
         return (std::max<size_t>(n, 1) + g - 1) & ~(g - 1);
     }
 
+    // best fit over all chunks; caller holds mu
+    void *carve(size_t n) {
+        Chunk *bc = nullptr;
+        size_t boff = 0, blen = SIZE_MAX;
+        for (Chunk *c : chunks)
+            for (auto &f : c->free)
+                if (f.second >= n && f.second < blen) {
+                    bc = c;
+                    boff = f.first;
+                    blen = f.second;
+                }
+        if (!bc) return nullptr;
+        bc->free.erase(boff);
+        if (blen > n) bc->free[boff + n] = blen - n;
+        bc->used += n;
+        void *p = bc->base + boff;
+        live[p] = {bc, n};
+        return p;
+    }
+
     void *alloc(size_t n) {
         n = round(n);
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            auto it = free_blocks.lower_bound(n);
-            if (it != free_blocks.end() && it->first <= n + n / 2 + ((size_t)2 << 20)) {
-                void *p = it->second;
-                free_blocks.erase(it);
-                return p;
-            }
-        }
-        void *p = nullptr;
-        if (hipMalloc(&p, n) != hipSuccess) {
-            (void)hipGetLastError();
-            trim();
-            if (hipMalloc(&p, n) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-        }
         std::lock_guard<std::mutex> lk(mu);
-        sizes[p] = n;
-        return p;
+        if (void *p = carve(n)) return p;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const size_t sz = std::max(n, chunk_min);
+            void *base = nullptr;
+            if (hipMalloc(&base, sz) == hipSuccess) {
+                Chunk *c = new Chunk();
+                c->base = static_cast<char *>(base);
+                c->size = sz;
+                c->free[0] = sz;
+                chunks.push_back(c);
+                return carve(n);
+            }
+            (void)hipGetLastError();
+            if (attempt == 0) release_empty();
+        }
+        return nullptr;
     }
 
     void release(void *p, hipStream_t st) {
@@ -90,25 +116,49 @@ struct DeviceCache {
         // the block may next serve another stream: let this one finish with it
         if (st) (void)hipStreamSynchronize(st);
         std::lock_guard<std::mutex> lk(mu);
-        auto it = sizes.find(p);
-        if (it == sizes.end()) return;
-        free_blocks.emplace(it->second, p);
+        auto it = live.find(p);
+        if (it == live.end()) return;
+        Chunk *c = it->second.first;
+        size_t off = static_cast<char *>(p) - c->base, len = it->second.second;
+        live.erase(it);
+        c->used -= len;
+        auto nx = c->free.lower_bound(off);
+        if (nx != c->free.end() && off + len == nx->first) {
+            len += nx->second;
+            nx = c->free.erase(nx);
+        }
+        if (nx != c->free.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        c->free[off] = len;
     }
 
-    void trim() {
-        std::lock_guard<std::mutex> lk(mu);
-        for (auto &kv : free_blocks) {
-            (void)hipFree(kv.second);
-            sizes.erase(kv.second);
+    // caller holds mu
+    void release_empty() {
+        std::vector<Chunk *> keep;
+        for (Chunk *c : chunks) {
+            if (c->used == 0) {
+                (void)hipFree(c->base);
+                delete c;
+            } else {
+                keep.push_back(c);
+            }
         }
-        free_blocks.clear();
+        chunks.swap(keep);
     }
 
     void destroy() {
         std::lock_guard<std::mutex> lk(mu);
-        for (auto &kv : sizes) (void)hipFree(kv.first);
-        sizes.clear();
-        free_blocks.clear();
+        for (Chunk *c : chunks) {
+            (void)hipFree(c->base);
+            delete c;
+        }
+        chunks.clear();
+        live.clear();
     }
 };
 
@@ -154,6 +204,7 @@ struct sline_server {
     };
     std::vector<Worker> workers;
     DeviceCache cache;                            // device memory of every worker
+    bool log = false;                             // SLINE_SERVER_LOG set: one line per batch
     std::string last_error;
 };
 
@@ -209,8 +260,19 @@ void worker_loop(sline_server *S, int wi) {
                 q.worker = wi;
             }
         }
+        const int64_t t_run = now_ns();
         const sline_status st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), 0, outs.data());
         const int64_t t_done = now_ns();
+        if (S->log) {
+            int64_t pairs = 0, big = 0;
+            for (int32_t g = 0; g < G; ++g) {
+                pairs += st == SLINE_OK ? outs[g].n_pairs : 0;
+                big += Hs[g].n_edges >= 500000;
+            }
+            fprintf(stderr, "sline-server: worker %d batch of %d (%lld large, est %.2f GB) status %d "
+                    "pairs %lld %.1f ms\n", wi, G, (long long)big, est / 1e9, st, (long long)pairs,
+                    (t_done - t_run) / 1e6);
+        }
         std::string err = st == SLINE_OK ? std::string() : std::string(sline_last_error(W.ctx));
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -262,6 +324,7 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
     al.alloc = cache_alloc;
     al.free = cache_free;
     al.user = &S->cache;
+    S->log = getenv("SLINE_SERVER_LOG") != nullptr;
     S->workers.resize(n_workers);
     for (auto &W : S->workers) {
         if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
