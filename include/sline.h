@@ -114,6 +114,10 @@ typedef struct {
     int64_t heavy_wedges; /* wedges it walked                                     */
     int64_t heavy_pairs;  /* pairs it produced                                    */
     double ms_tasks;      /* its run time (SLINE_PROFILE)                         */
+    /* sline_build_spgemm only                                                */
+    int64_t product_nnz;  /* entries of the materialized product H H^T          */
+    double ms_product;    /* product time (host clock)                          */
+    double ms_filter;     /* filter time (host clock)                           */
 } sline_stats;
 
 /* Launch parameters of the counting stage (they change speed, never the
@@ -161,6 +165,17 @@ void sline_destroy(sline_ctx *ctx);
  * s larger than every item gives an empty result, not an error. */
 sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
                          uint32_t flags, sline_edges *out);
+
+/* Companion route to the same result (Sec. IV-D): the product C = H H^T
+ * (H* H*^T for dual = 1) with both triangles and the diagonal, computed row
+ * by row (Gustavson) with the LDS hash accumulators of sline_build and
+ * materialized in full -- nnz(C) = 2 |L_1| + (non-empty items) entries of 12
+ * bytes -- then filtered to the pairs with b > a and w >= s.  No degree
+ * pruning: the product does not depend on s.  Arguments, output, errors and
+ * the capacity protocol as in sline_build (SLINE_ECAPACITY computes the
+ * product again on the retry).  Built for comparison with sline_build. */
+sline_status sline_build_spgemm(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
+                                uint32_t flags, sline_edges *out);
 
 /* Build L_{s[g]} of every hypergraph Hs[g] (dual[g] as in sline_build) in
  * one pass of the counting pipeline: the graphs' items are numbered one after

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <string>
 #include <vector>
@@ -417,6 +418,7 @@ struct ItemS {
     const int32_t *s_item = nullptr;
     const int32_t *item_end = nullptr;  // one past the last item of each item's graph
     int32_t s_min = 1, s_max = 1;
+    bool full = false;  // product mode (the SpGEMM companion): every b, b = a included
 };
 
 sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
@@ -557,7 +559,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     // 6. wedge counts, tasks
     const Tuning tu = c->tune;
     hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, IS.s_item, ptrS, itmS, L.cost, L.start,
-                             L.totals),
+                             L.totals, IS.full ? 1 : 0),
               "cost");
     hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS, L.start,
                                     L.cost),
@@ -606,6 +608,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.s = s;
     C.s_item = IS.s_item;
     C.item_end = IS.item_end;
+    C.full = IS.full ? 1 : 0;
     C.cost = L.cost;
     C.start = L.start;
     C.task_item = TL.item;
@@ -1041,6 +1044,132 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     return r;
 }
 
+// ------------------------------------------------------ SpGEMM companion
+
+// L_s by the product route (Sec. IV-D): C = H H^T with both triangles and the
+// diagonal, computed row by row (Gustavson) with the same LDS hash
+// accumulators, materialized in full, then filtered to b > a, w >= s.  No
+// degree pruning or lookup-only members: the product does not know s.
+sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
+                         sline_edges *out) {
+    if (!out) {
+        set_err(c, "out is NULL");
+        return SLINE_EINVAL;
+    }
+    if (s < 1 || (dual != 0 && dual != 1) || H.n_edges < 0 || H.n_vertices < 0) {
+        set_err(c, "invalid argument (s >= 1, dual in {0,1}, sizes >= 0 required)");
+        return SLINE_EINVAL;
+    }
+    if (out->capacity < 0 || (out->capacity > 0 && (!out->a || !out->b || !out->w))) {
+        set_err(c, "output buffers: capacity > 0 requires a, b and w");
+        return SLINE_EINVAL;
+    }
+    c->pending.valid = false;
+    drop_batch_pending(c);
+    release_pool(c);
+    hipStream_t st = c->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    sline_edges P{};
+    ItemS IS;
+    IS.full = true;
+    const sline_status r = build_core(c, H, 1, dual, flags, &P, IS);
+    release_pool(c);
+    if (r != SLINE_OK) return r;
+    sync(c, "product");
+    auto t1 = std::chrono::steady_clock::now();
+    const int64_t nP = P.n_pairs;
+    const size_t pbytes = sizeof(int32_t) * (size_t)std::max<int64_t>(nP, 1);
+    auto free_product = [&]() {
+        if (P.a) {
+            (void)hipStreamSynchronize(st);
+            dev_free(c, P.a, pbytes);
+            dev_free(c, P.b, pbytes);
+            dev_free(c, P.w, pbytes);
+        }
+    };
+    try {
+        const int64_t tiles = (nP + kFilterTile - 1) / kFilterTile;
+        int64_t total = 0;
+        int32_t *cnt = nullptr;
+        int64_t *off = nullptr, *part = nullptr;
+        void *fw = nullptr;
+        size_t fw_bytes = 0;
+        if (tiles > 0) {
+            Arena sz;
+            sz.take<int32_t>(tiles);
+            sz.take<int64_t>(tiles + 1);
+            sz.take<int64_t>(scan_partials(tiles + 1));
+            fw_bytes = sz.off + 4096;
+            fw = dev_alloc(c, fw_bytes);
+            if (!fw) {
+                set_err(c, "filter workspace allocation failed");
+                throw Fail{SLINE_ENOMEM};
+            }
+            Arena A;
+            A.base = reinterpret_cast<char *>(fw);
+            cnt = A.take<int32_t>(tiles);
+            off = A.take<int64_t>(tiles + 1);
+            part = A.take<int64_t>(scan_partials(tiles + 1));
+            hip_check(c, launch_product_filter(st, P.a, P.b, P.w, nP, s, cnt, nullptr, nullptr, nullptr,
+                                               nullptr),
+                      "product filter count");
+            hip_check(c, launch_scan_i32_to_i64(st, cnt, tiles, off, part), "product filter scan");
+            hip_check(c, hipMemcpyAsync(c->host, off + tiles, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+                      "read filtered size");
+            sync(c, "product filter count");
+            total = c->host[0];
+        }
+        if (out->capacity > 0 && out->capacity < total) {
+            out->n_pairs = total;
+            if (fw) dev_free(c, fw, fw_bytes);
+            free_product();
+            set_err(c, "capacity too small");
+            return SLINE_ECAPACITY;
+        }
+        int32_t *a = out->a, *b = out->b, *w = out->w;
+        bool owned = false;
+        if (out->capacity == 0) {
+            a = b = w = nullptr;
+            if (total > 0) {
+                const size_t bytes = sizeof(int32_t) * (size_t)total;
+                a = (int32_t *)dev_alloc(c, bytes);
+                b = (int32_t *)dev_alloc(c, bytes);
+                w = (int32_t *)dev_alloc(c, bytes);
+                owned = true;
+                if (!a || !b || !w) {
+                    dev_free(c, a, bytes);
+                    dev_free(c, b, bytes);
+                    dev_free(c, w, bytes);
+                    set_err(c, "output allocation failed");
+                    throw Fail{SLINE_ENOMEM};
+                }
+            }
+        }
+        if (total > 0)
+            hip_check(c, launch_product_filter(st, P.a, P.b, P.w, nP, s, cnt, off, a, b, w),
+                      "product filter write");
+        sync(c, "product filter");
+        if (fw) dev_free(c, fw, fw_bytes);
+        (void)owned;
+        if (out->capacity == 0) {
+            out->a = a;
+            out->b = b;
+            out->w = w;
+        }
+        out->n_pairs = total;
+    } catch (...) {
+        free_product();
+        throw;
+    }
+    free_product();
+    auto t2 = std::chrono::steady_clock::now();
+    c->stats.product_nnz = nP;
+    c->stats.n_pairs = out->n_pairs;
+    c->stats.ms_product = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->stats.ms_filter = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    return SLINE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1134,6 +1263,26 @@ sline_status sline_build_batch(sline_ctx *c, int32_t n_graphs, const sline_csr *
     } catch (const std::bad_alloc &) {
         drop_batch_pending(c);
         c->pending.valid = false;
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_build_spgemm(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uint32_t flags,
+                                sline_edges *out) {
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return spgemm_impl(c, H, s, dual, flags, out);
+    } catch (const Fail &f) {
+        release_pool(c);
+        return f.st;
+    } catch (const std::bad_alloc &) {
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;
     }

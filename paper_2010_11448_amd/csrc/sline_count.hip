@@ -751,7 +751,7 @@ __device__ __forceinline__ void init_cursors(const CountArgs &A, int32_t a, int3
             const int32_t st = A.start[k];
             lookm |= (uint32_t)(st < 0) << i;
             int32_t c = st & kStartMask;
-            if (lo > a + 1) c = lower_bound(A.itmS, c, e, lo);
+            if (lo > (A.full ? 0 : a + 1)) c = lower_bound(A.itmS, c, e, lo);
             cur[i] = c;
             end[i] = e;
         }
@@ -770,9 +770,10 @@ __device__ __forceinline__ int32_t task_parts(int64_t cost, int32_t small_max, i
     return (int32_t)((cost + target - 1) / target);
 }
 
-__device__ __forceinline__ void task_range(int32_t a, int32_t N, int32_t p, int32_t P, int32_t &lo,
-                                           int32_t &hi) {
-    const int64_t first = (int64_t)a + 1, span = (int64_t)N - first;
+// Sub-range p of P of the candidate range [first, N) of an item.
+__device__ __forceinline__ void task_range(int32_t first_id, int32_t N, int32_t p, int32_t P,
+                                           int32_t &lo, int32_t &hi) {
+    const int64_t first = first_id, span = (int64_t)N - first;
     lo = (int32_t)(first + span * p / P);
     hi = (int32_t)(first + span * (p + 1) / P);
 }
@@ -815,9 +816,10 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         int32_t cur[kR], end[kR];
         uint32_t lookm;
         const int32_t nend = A.item_end ? A.item_end[a] : A.N;
-        init_cursors<kWave>(A, a, a + 1, k0, k1, cur, end, lookm);
+        init_cursors<kWave>(A, a, A.full ? 0 : a + 1, k0, k1, cur, end, lookm);
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
-            A, S, a, A.s_item ? A.s_item[a] : A.s, nend, t, a + 1, nend, want, count_bits(k1 - k0),
+            A, S, a, A.s_item ? A.s_item[a] : A.s, nend, t, A.full ? 0 : a + 1, nend, want,
+            count_bits(k1 - k0),
             k0, k1, cur, end, lookm, passes);
         if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
@@ -869,7 +871,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         bool fresh = true;  // cursors must be placed at the range start
         for (int32_t q = p0; q < p1; ++q) {
             int32_t lo, hi;
-            task_range(a, nend, q, P, lo, hi);
+            task_range(A.full ? 0 : a + 1, nend, q, P, lo, hi);
             const int32_t t = t0 + (q - p0);
             if (A.mode == kModeFill && A.need && !A.need[t]) {
                 fresh = true;

@@ -88,9 +88,19 @@ hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itm
 // Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
 // in N_s(v) for member incidence k of a kept item a) and the run totals:
 // totals[0] = kept items, [1] = kept incidences, [2] = wedges.
+// full != 0 (product mode): start[k] = the first entry of N_s(v) and W_a counts
+// every b in the lists, a itself included.
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
-                       int64_t *cost, int32_t *start, int64_t *totals);
+                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full = 0);
+
+// Keep the entries (a, b, w) with b > a and w >= s of a row-sorted product,
+// in order: pass 1 (out_a == nullptr) counts per block into cnt, pass 2 writes
+// at the exclusive scan off of those counts.  kFilterTile entries per block.
+constexpr int kFilterTile = 4096;
+hipError_t launch_product_filter(hipStream_t st, const int32_t *a, const int32_t *b, const int32_t *w,
+                                 int64_t n, int32_t s, int32_t *cnt, const int64_t *off,
+                                 int32_t *out_a, int32_t *out_b, int32_t *out_w);
 
 // Lookup-only members (insertion cutoff, s > 1): a candidate b with
 // |S_a & S_b| >= s lies in at least s of the lists N_s(v), v in S_a, so if up
@@ -139,6 +149,7 @@ struct CountArgs {
     int32_t N, s;
     const int32_t *s_item;       // per-item s (batches), or null: s for every item
     const int32_t *item_end;     // per item: one past the last item of its graph (batches), or null: N
+    int32_t full;                // product mode: every candidate b (both triangles and b = a)
     const int64_t *cost;         // W_a per item
     const int32_t *start;        // back-pointers per item incidence (see launch_cost)
     const int32_t *task_item, *task_part;

@@ -341,7 +341,8 @@ __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32
 __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t *memI,
                                               int32_t N, int32_t s, const int32_t *s_item,
                                               const int32_t *ptrS, const int32_t *itmS,
-                                              int64_t *cost, int32_t *start, int64_t *totals) {
+                                              int64_t *cost, int32_t *start, int64_t *totals,
+                                              int32_t full) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
         for (int32_t k = b + lane; k < e; k += kWave) {
             const int32_t v = memI[k];
             const int32_t lo = ptrS[v], hi = ptrS[v + 1];
-            const int32_t st = upper_bound(itmS, lo, hi, (int32_t)a);
+            const int32_t st = full ? lo : upper_bound(itmS, lo, hi, (int32_t)a);
             start[k] = st;
             c += hi - st;
         }
@@ -419,9 +420,55 @@ __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const 
     }
 }
 
+// Product filter, one block per tile of kFilterTile entries (256 threads x
+// 16): pass 1 counts the kept entries of the tile, pass 2 writes them at
+// off[tile] in their original order.
+__global__ __launch_bounds__(256) void k_product_filter(const int32_t *a, const int32_t *b,
+                                                        const int32_t *w, int64_t n, int32_t s,
+                                                        int32_t *cnt, const int64_t *off,
+                                                        int32_t *oa, int32_t *ob, int32_t *ow) {
+    __shared__ int32_t sh[kScanThreads / kWave + 1];
+    constexpr int PER = kFilterTile / 256;
+    const int64_t t0 = (int64_t)blockIdx.x * kFilterTile;
+    int32_t keep[PER];
+    int32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int64_t k = t0 + (int64_t)threadIdx.x * PER + i;
+        keep[i] = k < n && b[k] > a[k] && w[k] >= s;
+        mine += keep[i];
+    }
+    int32_t total;
+    const int32_t ex = block_excl_scan<int32_t>(mine, sh, total);
+    if (!oa) {
+        if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+        return;
+    }
+    int64_t o = off[blockIdx.x] + ex;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        if (keep[i]) {
+            const int64_t k = t0 + (int64_t)threadIdx.x * PER + i;
+            oa[o] = a[k];
+            ob[o] = b[k];
+            ow[o] = w[k];
+            ++o;
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+
+hipError_t launch_product_filter(hipStream_t st, const int32_t *a, const int32_t *b, const int32_t *w,
+                                 int64_t n, int32_t s, int32_t *cnt, const int64_t *off,
+                                 int32_t *out_a, int32_t *out_b, int32_t *out_w) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + kFilterTile - 1) / kFilterTile;
+    k_product_filter<<<(unsigned)tiles, 256, 0, st>>>(a, b, w, n, s, cnt, off, out_a, out_b, out_w);
+    return hipGetLastError();
+}
 
 hipError_t launch_check_rowptr(hipStream_t st, const int32_t *rp, int32_t m, int32_t *err) {
     k_check_rowptr<<<grid_for((int64_t)m + 1, 256), 256, 0, st>>>(rp, m, err);
@@ -542,10 +589,10 @@ hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itm
 
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
-                       int64_t *cost, int32_t *start, int64_t *totals) {
+                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full) {
     if (N <= 0) return hipSuccess;
     k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(
-        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals);
+        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals, full);
     return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ class sline_stats(ctypes.Structure):
                  "n_heavy", "passes")] + [(k, ctypes.c_double) for k in
                 ("ms_transpose", "ms_prepare", "ms_count", "ms_scan", "ms_fill")] + [
                 (k, ctypes.c_int64) for k in ("heavy_nnz", "heavy_wedges", "heavy_pairs")] + [
-                ("ms_tasks", ctypes.c_double)]
+                ("ms_tasks", ctypes.c_double), ("product_nnz", ctypes.c_int64),
+                ("ms_product", ctypes.c_double), ("ms_filter", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
@@ -95,6 +96,9 @@ SIGNATURES = {
     "sline_destroy": (None, [ctypes.c_void_p]),
     "sline_build": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
+    "sline_build_spgemm": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_uint32,
+                                            ctypes.POINTER(sline_edges)]),
     "sline_build_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sline_csr),
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
@@ -268,14 +272,17 @@ class Context:
                          int(row_ptr.numel()) - 1, int(n_vertices))
 
     def build(self, row_ptr, col, n_vertices: int, s: int, dual: int = 0,
-              flags: int = 0) -> LineGraph:
-        """L_s(H) (or L_s(H*) with dual=1) as int32 device tensors sorted by (a, b)."""
+              flags: int = 0, spgemm: bool = False) -> LineGraph:
+        """L_s(H) (or L_s(H*) with dual=1) as int32 device tensors sorted by (a, b).
+
+        spgemm=True takes the product route (sline_build_spgemm)."""
         import torch
+        fn = load().sline_build_spgemm if spgemm else load().sline_build
         H = self.csr(row_ptr, col, n_vertices)
         dev = torch.device("cuda", self.device)
         probe = torch.empty(3, dtype=torch.int32, device=dev)
         out = sline_edges(0, 1, probe[0:1].data_ptr(), probe[1:2].data_ptr(), probe[2:3].data_ptr())
-        st = sline_build(self.ctx, H, s, dual, flags, out)
+        st = fn(self.ctx, H, s, dual, flags, ctypes.byref(out))
         if st == SLINE_OK:
             n = int(out.n_pairs)  # 0 or 1 pair: it sits in the probe buffers
             return LineGraph(probe[0:n].clone(), probe[1:1 + n].clone(), probe[2:2 + n].clone())
@@ -286,7 +293,7 @@ class Context:
         b = torch.empty(n, dtype=torch.int32, device=dev)
         w = torch.empty(n, dtype=torch.int32, device=dev)
         out = sline_edges(0, n, a.data_ptr(), b.data_ptr(), w.data_ptr())
-        st = sline_build(self.ctx, H, s, dual, flags, out)
+        st = fn(self.ctx, H, s, dual, flags, ctypes.byref(out))
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
         return LineGraph(a, b, w)
