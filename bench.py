@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--budget-gb", type=float, default=160.0)
     p.add_argument("--workers", type=int, default=2)
     p.add_argument("--graphs", type=int, default=512, help="batch form: number of graphs")
+    p.add_argument("--spgemm", action="store_true",
+                   help="plain/dual forms: take the product route (sline_build_spgemm)")
     p.add_argument("--autotune", action="store_true", help="batch form: tune launch parameters first")
     p.add_argument("--tune-budget", type=float, default=90.0)
     p.add_argument("--s", default=None, help="comma-separated s values")
@@ -366,7 +368,7 @@ def main():
     def step(record):
         for s in s_list:
             t0 = time.perf_counter()
-            L = ctx.build(rp, col, g.n_vertices, s, dual, flags)
+            L = ctx.build(rp, col, g.n_vertices, s, dual, flags, spgemm=args.spgemm)
             t1 = time.perf_counter()
             if record:
                 per_s[s].append((t1 - t0, ctx.stats()))
@@ -409,6 +411,8 @@ def main():
             "ms_scan": float(np.median([r[1]["ms_scan"] for r in recs])),
             "ms_fill": float(np.median([r[1]["ms_fill"] for r in recs])),
             "heavy_items": st["n_heavy"], "small_items": st["n_small"], "passes": st["passes"],
+            "product_nnz": st["product_nnz"], "ms_product": st["ms_product"],
+            "ms_filter": st["ms_filter"],
         }
     achieved = alg_bytes / 1e9 / (task_ms / 1000.0) if task_ms > 0 else 0.0
     tr = committed_traffic(args.form if args.scale == 1.0 and not args.s else None)
@@ -426,7 +430,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": g.meta.get("workload", "powerlaw") + (" dual" if dual else ""),
+        "config": {"workload": g.meta.get("workload", "powerlaw") + (" dual" if dual else "") +
+                   (" spgemm" if args.spgemm else ""),
                    "n_edges": g.n_edges, "n_vertices": g.n_vertices, "nnz": g.nnz,
                    "s": list(s_list), "dual": dual, "builds_per_step": len(s_list)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -590,7 +590,9 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     mark(c, 2);
     // 7. one counting pass: pairs per task, each range's pairs staged in a pool
     const int64_t want_pool = S.wedges / IS.s_min;  // every pair of L_s accounts for >= s wedges
-    const int64_t pool_cap = want_pool > 0 ? acquire_pool(c, want_pool) : 0;
+    // the product route counts and fills in two passes (symbolic, then
+    // numeric), as SpGEMM does: its product is too large to stage as well
+    const int64_t pool_cap = (want_pool > 0 && !IS.full) ? acquire_pool(c, want_pool) : 0;
     hip_check(c, launch_fill_i32(st, TL.need, T, 0), "zero flags");
     // unused records of a reserved log chunk must read as empty
     hip_check(c, launch_fill_i32(st, reinterpret_cast<int32_t *>(TL.log),
