@@ -197,6 +197,7 @@ struct Layout {
     int32_t *err, *seg, *queue, *tcounts;
     int64_t *totals, *passes;
     int32_t *rowid, *degT, *ptrT, *fillT, *colT, *mid_list, *big_list;
+    int32_t *kT = nullptr, *posT = nullptr;  // transposed position <-> incidence
     int32_t *ptrS, *cntS, *itmS;
     int64_t *cost, *tbase, *part64;
     int32_t *part32, *ntask, *start;
@@ -215,6 +216,8 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
     L.ptrT = A.take<int32_t>(n + 1);
     L.fillT = A.take<int32_t>(n);
     L.colT = A.take<int32_t>(nnz);
+    L.kT = A.take<int32_t>(nnz);
+    L.posT = A.take<int32_t>(nnz);
     L.mid_list = A.take<int32_t>(n);
     L.big_list = A.take<int32_t>(n);
     const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m}) + 1);
@@ -291,7 +294,10 @@ void transpose(sline_ctx *c, const Layout &L, const int32_t *col, int32_t n, int
     sync(c, "transpose");
     const int32_t *hs = reinterpret_cast<const int32_t *>(c->host);
     const int32_t nbig = hs[1], maxdeg = hs[2];
-    if (nbig == 0) return;
+    if (nbig == 0) {
+        hip_check(c, launch_transpose_fix(st, nnz, L.rowid, L.colT, L.kT, L.posT), "transpose fix");
+        return;
+    }
     // rows longer than the LDS sort: bitonic network in global memory, one row at a time
     int32_t n2 = 1;
     while (n2 < maxdeg) n2 <<= 1;
@@ -331,6 +337,7 @@ void transpose(sline_ctx *c, const Layout &L, const int32_t *col, int32_t n, int
             hip_check(c, launch_segsort_big_store(st, tmp, len, L.colT + b), "long row store");
         }
         sync(c, "long row sort");
+        hip_check(c, launch_transpose_fix(st, nnz, L.rowid, L.colT, L.kT, L.posT), "transpose fix");
     } catch (...) {
         dev_free(c, tmp, sizeof(int32_t) * (size_t)n2);
         free(big);
@@ -543,6 +550,9 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const int32_t *memI = dual ? L.colT : H.col_idx;
     const int32_t *ptrM = dual ? H.row_ptr : L.ptrT;
     const int32_t *itmM = dual ? H.col_idx : L.colT;
+    // back-pointer maps: item incidence -> member-list position, and back
+    const int32_t *map = dual ? L.kT : L.posT;
+    const int32_t *inv = dual ? L.posT : L.kT;
     // 5. s filter
     const int32_t *ptrS = ptrM, *itmS = itmM;
     if (filt) {
@@ -551,15 +561,17 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
                   "filter count");
         hip_check(c, launch_scan_i32(st, L.cntS, M, L.ptrS, L.part32), "filter scan");
         hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, IS.s_item, L.ptrS, L.cntS,
-                                   L.itmS),
+                                   L.itmS, inv, L.start),
                   "filter fill");
         ptrS = L.ptrS;
         itmS = L.itmS;
     }
     // 6. wedge counts, tasks
     const Tuning tu = c->tune;
+    if (!filt && !IS.full)
+        hip_check(c, launch_start_from_map(st, nnz, map, L.start), "back-pointers");
     hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, IS.s_item, ptrS, itmS, L.cost, L.start,
-                             L.totals, IS.full ? 1 : 0),
+                             L.totals, IS.full ? 1 : 0, IS.full ? 0 : 1),
               "cost");
     hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS, L.start,
                                     L.cost),

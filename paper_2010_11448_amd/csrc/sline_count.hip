@@ -899,10 +899,21 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         __syncthreads();
     }
     if (A.passes && A.mode != kModeFill) {
+        // one atomic per counter and workgroup (same-address atomics serialize)
         unsigned long long *wk = (unsigned long long *)A.passes;
-        if (my_wedges) atomicAdd(&wk[2], (unsigned long long)my_wedges);
-        if (threadIdx.x == 0 && my_nnz) atomicAdd(&wk[1], (unsigned long long)my_nnz);
-        if (threadIdx.x == 0 && my_pairs) atomicAdd(&wk[3], (unsigned long long)my_pairs);
+        int64_t w = my_wedges;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) w += __shfl_xor(w, d, kWave);
+        __shared__ int64_t red[NT / kWave];
+        if (lane_id() == 0) red[threadIdx.x / kWave] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int i = 0; i < NT / kWave; ++i) t += red[i];
+            if (t) atomicAdd(&wk[2], (unsigned long long)t);
+            if (my_nnz) atomicAdd(&wk[1], (unsigned long long)my_nnz);
+            if (my_pairs) atomicAdd(&wk[3], (unsigned long long)my_pairs);
+        }
     }
     if (threadIdx.x == 0 && passes && A.passes)
         atomicAdd((unsigned long long *)A.passes, (unsigned long long)passes);

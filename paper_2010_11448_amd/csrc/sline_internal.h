@@ -64,8 +64,15 @@ hipError_t launch_scan_i32(hipStream_t st, const int32_t *in, int64_t n, int32_t
 hipError_t launch_scan_i32_to_i64(hipStream_t st, const int32_t *in, int64_t n, int64_t *out,
                                   int64_t *partial);
 
+// colT receives incidence indices (sorted per row like row ids); after the
+// sorts launch_transpose_fix turns them into row ids and records the maps
+// kT (transposed position -> incidence) and posT (incidence -> position).
 hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *rowid, int64_t nnz,
                           int32_t n, const int32_t *ptrT, int32_t *fill, int32_t *colT);
+hipError_t launch_transpose_fix(hipStream_t st, int64_t nnz, const int32_t *rowid, int32_t *colT,
+                                int32_t *kT, int32_t *posT);
+// start[k] = map[k] + 1 (unfiltered member lists)
+hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map, int32_t *start);
 // Sorts every transposed row ascending.  `counts` holds 3 int32 (mid, big,
 // max degree), `mid_list`/`big_list` hold up to n entries each.
 hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
@@ -80,10 +87,14 @@ hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t 
                                     int32_t *dst);
 
 // Filtered membership lists N_s(v): the items b of v's list with size >=
-// s (s_item[b] when s_item is given: every item carries its own s).
+// s (s_item[b] when s_item is given: every item carries its own s).  With
+// start given, pass 2 also writes the back-pointer of every kept entry:
+// start[inv[k]] = (its position in itmS) + 1, inv mapping member-list
+// positions to item incidences.
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
                          const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
-                         int32_t *cntS, int32_t *itmS);
+                         int32_t *cntS, int32_t *itmS, const int32_t *inv = nullptr,
+                         int32_t *start = nullptr);
 
 // Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
 // in N_s(v) for member incidence k of a kept item a) and the run totals:
@@ -92,7 +103,8 @@ hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itm
 // every b in the lists, a itself included.
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
-                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full = 0);
+                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full = 0,
+                       int32_t have_start = 0);
 
 // Keep the entries (a, b, w) with b > a and w >= s of a row-sorted product,
 // in order: pass 1 (out_a == nullptr) counts per block into cnt, pass 2 writes

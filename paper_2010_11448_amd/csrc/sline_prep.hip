@@ -211,8 +211,30 @@ __global__ void k_scatter(const int32_t *col, const int32_t *rowid, int64_t nnz,
         int32_t v = col[k];
         if (v < 0 || v >= n) continue;
         int32_t p = ptrT[v] + atomicAdd(&fill[v], 1);
+        colT[p] = (int32_t)k;  // incidence index: within a row it orders like the row id
+    }
+}
+
+// After the per-row sort of incidence indices: colT[p] becomes the row id of
+// incidence kT[p] = colT[p], and posT[k] the transposed position of incidence
+// k (kT / posT may be null).
+__global__ void k_transpose_fix(int64_t nnz, const int32_t *rowid, int32_t *colT, int32_t *kT,
+                                int32_t *posT) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = colT[p];
+        if (kT) kT[p] = k;
+        if (posT) posT[k] = (int32_t)p;
         colT[p] = rowid[k];
     }
+}
+
+// start[k] = map[k] + 1 for every item incidence k (lists not filtered: the
+// first item after a in N(v) follows a's own position in the list).
+__global__ void k_start_from_map(int64_t nnz, const int32_t *map, int32_t *start) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * blockDim.x)
+        start[k] = map[k] + 1;
 }
 
 __global__ void k_segsort_classify(const int32_t *ptr, int32_t n, int32_t *mid_list,
@@ -311,7 +333,8 @@ __global__ void k_bitonic_step(int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
 __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32_t *itmM,
                                                 int32_t M, const int32_t *ptrI, int32_t s,
                                                 const int32_t *s_item, const int32_t *ptrS,
-                                                int32_t *cntS, int32_t *itmS) {
+                                                int32_t *cntS, int32_t *itmS, const int32_t *inv,
+                                                int32_t *start) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -327,7 +350,12 @@ __global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32
                 keep = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s);
             }
             const uint64_t bal = __ballot(keep);
-            if (itmS && keep) itmS[run + lanes_below(bal)] = it;
+            if (itmS && keep) {
+                const int32_t q = run + (int32_t)lanes_below(bal);
+                itmS[q] = it;
+                // the kept item's own entry: its walk over v starts just after it
+                if (start) start[inv[k]] = q + 1;
+            }
             run += __popcll(bal);
         }
         if (!itmS && lane == 0) cntS[v] = run;
@@ -342,7 +370,7 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
                                               int32_t N, int32_t s, const int32_t *s_item,
                                               const int32_t *ptrS, const int32_t *itmS,
                                               int64_t *cost, int32_t *start, int64_t *totals,
-                                              int32_t full) {
+                                              int32_t full, int32_t have_start) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -357,8 +385,13 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
         for (int32_t k = b + lane; k < e; k += kWave) {
             const int32_t v = memI[k];
             const int32_t lo = ptrS[v], hi = ptrS[v + 1];
-            const int32_t st = full ? lo : upper_bound(itmS, lo, hi, (int32_t)a);
-            start[k] = st;
+            int32_t st;
+            if (have_start) {
+                st = start[k];
+            } else {
+                st = full ? lo : upper_bound(itmS, lo, hi, (int32_t)a);
+                start[k] = st;
+            }
             c += hi - st;
         }
         c = wave_sum(c);
@@ -367,10 +400,19 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
         kept_nnz += e - b;
         wedges += c;
     }
-    if (lane == 0 && kept) {
-        atomicAdd((unsigned long long *)&totals[0], (unsigned long long)kept);
-        atomicAdd((unsigned long long *)&totals[1], (unsigned long long)kept_nnz);
-        atomicAdd((unsigned long long *)&totals[2], (unsigned long long)wedges);
+    // one atomic per counter and block (same-address atomics serialize)
+    __shared__ int64_t red[3][256 / kWave];
+    const int wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][wid] = kept;
+        red[1][wid] = kept_nnz;
+        red[2][wid] = wedges;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int64_t t = 0;
+        for (int w = 0; w < 256 / kWave; ++w) t += red[threadIdx.x][w];
+        if (t) atomicAdd((unsigned long long *)&totals[threadIdx.x], (unsigned long long)t);
     }
 }
 
@@ -540,6 +582,19 @@ hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *row
     return hipGetLastError();
 }
 
+hipError_t launch_transpose_fix(hipStream_t st, int64_t nnz, const int32_t *rowid, int32_t *colT,
+                                int32_t *kT, int32_t *posT) {
+    if (nnz <= 0) return hipSuccess;
+    k_transpose_fix<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(nnz, rowid, colT, kT, posT);
+    return hipGetLastError();
+}
+
+hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map, int32_t *start) {
+    if (nnz <= 0) return hipSuccess;
+    k_start_from_map<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(nnz, map, start);
+    return hipGetLastError();
+}
+
 hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
                                    int32_t *mid_list, int32_t *big_list, int32_t *counts) {
     if (n <= 0) return hipSuccess;
@@ -580,19 +635,20 @@ hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t 
 
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
                          const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
-                         int32_t *cntS, int32_t *itmS) {
+                         int32_t *cntS, int32_t *itmS, const int32_t *inv, int32_t *start) {
     if (M <= 0) return hipSuccess;
-    k_filter<<<grid_for((int64_t)M * kWave, 256, 65536), 256, 0, st>>>(ptrM, itmM, M, ptrI, s,
-                                                                       s_item, ptrS, cntS, itmS);
+    k_filter<<<grid_for((int64_t)M * kWave, 256, 65536), 256, 0, st>>>(
+        ptrM, itmM, M, ptrI, s, s_item, ptrS, cntS, itmS, inv, start);
     return hipGetLastError();
 }
 
 hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                        int32_t s, const int32_t *s_item, const int32_t *ptrS, const int32_t *itmS,
-                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full) {
+                       int64_t *cost, int32_t *start, int64_t *totals, int32_t full,
+                       int32_t have_start) {
     if (N <= 0) return hipSuccess;
-    k_cost<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(
-        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals, full);
+    k_cost<<<grid_for((int64_t)N * kWave, 256, 4096), 256, 0, st>>>(
+        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals, full, have_start);
     return hipGetLastError();
 }
 
