@@ -4,13 +4,21 @@
 // sline_build, stage by stage (every stage is a HIP kernel of this library):
 //   1. row_ptr check, nnz read-back                      (one host sync)
 //   2. row ids, member range / order checks
-//   3. transpose: degree histogram, scan, atomic scatter, per-row sort
-//                                                        (one host sync for long rows)
+//   3. transpose: degree histogram, scan, atomic scatter of incidence ids,
+//      per-row sort, then row ids and the position maps (one host sync for
+//      rows too long for the LDS sort)
 //   4. items / member lists chosen by the dual flag (H* swaps the roles, Sec. III)
-//   5. s-filtered member lists N_s(v) (degree-based pruning, Sec. IV-C)
-//   6. exact per-item wedge counts W_a, buckets (small / heavy by log2 W_a)
-//   7. count pass, exclusive scan of pairs per item      (one host sync)
-//   8. output allocation, fill pass                      (one host sync)
+//   5. s-filtered member lists N_s(v) (degree-based pruning, Sec. IV-C) and
+//      the back-pointer of every incidence of a kept item
+//   6. exact per-item wedge counts W_a, lookup-only members (s > 1), tasks
+//      (one-wave items and workgroup task groups)       (one host sync)
+//   7. one counting pass staging each range's pairs, exclusive scan of pairs
+//      per task                                          (one host sync)
+//   8. output allocation, staged ranges copied to their offsets, tasks
+//      without room counted again                      (one host sync)
+// sline_build_batch runs the same stages once over many graphs (their items
+// numbered one after the other, each with its own s), sline_build_spgemm runs
+// them in product mode and filters the product.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -951,9 +959,8 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     }
     // 3. XD and its transpose; 4. combined item CSR
     Arena sz;
-    auto plan = [&](Arena &A, Layout &X, int32_t *&xrp, int32_t *&len, int32_t *&ptrC,
+    auto plan = [&](Arena &A, Layout &X, int32_t *&len, int32_t *&ptrC,
                     int32_t *&memC, int32_t *&s_item, int32_t *&iend) {
-        xrp = A.take<int32_t>(E + 1);
         X.rowid = A.take<int32_t>(ZD);
         X.colT = A.take<int32_t>(ZD);
         X.degT = A.take<int32_t>(VD);
@@ -971,8 +978,8 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         X.cntS = A.take<int32_t>(ZD);  // XD columns
     };
     Layout X{};
-    int32_t *xrp, *len, *ptrC, *memC, *s_item, *iend;
-    plan(sz, X, xrp, len, ptrC, memC, s_item, iend);
+    int32_t *len, *ptrC, *memC, *s_item, *iend;
+    plan(sz, X, len, ptrC, memC, s_item, iend);
     void *big = dev_alloc(c, sz.off + 4096);
     if (!big) {
         set_err(c, "batch arrays allocation failed");
@@ -984,12 +991,12 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     try {
         Arena A;
         A.base = reinterpret_cast<char *>(big);
-        plan(A, X, xrp, len, ptrC, memC, s_item, iend);
+        plan(A, X, len, ptrC, memC, s_item, iend);
         int32_t *xcol = X.cntS;
         hip_check(c, launch_fill_i32(st, xcol, ZD, 0), "zero dual columns");
         hip_check(c, launch_fill_i32(st, X.rowid, ZD, 0), "zero dual rows");
         if (GD > 0 && E > 0) {
-            hip_check(c, launch_batch_concat(st, d_gr, d_dual_ids, d_dbase, GD, E, xrp, xcol, X.rowid,
+            hip_check(c, launch_batch_concat(st, d_gr, d_dual_ids, d_dbase, GD, E, xcol, X.rowid,
                                              d_err),
                       "dual rows");
             hip_check(c, launch_fill_i32(st, X.seg, 4, 0), "zero classes");

@@ -52,12 +52,12 @@ __global__ void k_batch_nnz(const BatchGraph *gr, int32_t G, int64_t *nnz, int32
     nnz[g] = z;
 }
 
-// One wave per row of XD (the dual graphs' rows, in graph order): row
-// pointer, columns shifted by vdbase, row ids; range and order checks.
+// One wave per row of XD (the dual graphs' rows, in graph order): columns
+// shifted by vdbase and the row id of every entry (what the transpose reads);
+// range and order checks.
 __global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, const int32_t *dual_ids,
                                                       const int64_t *dbase, int32_t GD, int64_t E,
-                                                      int32_t *xrp, int32_t *xcol, int32_t *xrow,
-                                                      int32_t *err) {
+                                                      int32_t *xcol, int32_t *xrow, int32_t *err) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -66,10 +66,6 @@ __global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, cons
         const BatchGraph d = gr[dual_ids[q]];
         const int32_t loc = (int32_t)(e - dbase[q]);
         const int32_t b = d.rp[loc], en = d.rp[loc + 1];
-        if (lane == 0) {
-            xrp[e] = (int32_t)(d.dzbase + b);
-            if (e == E - 1) xrp[E] = (int32_t)(d.dzbase + en);
-        }
         // a row outside [0, nnz) is reported and never read (its entries of
         // XD stay zero, so later kernels index safely until the error returns)
         if (b < 0 || en < b || en > d.nnz) {
@@ -195,11 +191,11 @@ hipError_t launch_batch_nnz(hipStream_t st, const BatchGraph *gr, int32_t G, int
 }
 
 hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32_t *dual_ids,
-                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xrp,
-                               int32_t *xcol, int32_t *xrow, int32_t *err) {
+                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xcol,
+                               int32_t *xrow, int32_t *err) {
     if (E <= 0) return hipSuccess;
-    k_batch_concat<<<grid_for(E * kWave, 256, 65536), 256, 0, st>>>(gr, dual_ids, dbase, GD, E, xrp,
-                                                                    xcol, xrow, err);
+    k_batch_concat<<<grid_for(E * kWave, 256, 65536), 256, 0, st>>>(gr, dual_ids, dbase, GD, E, xcol,
+                                                                    xrow, err);
     return hipGetLastError();
 }
 

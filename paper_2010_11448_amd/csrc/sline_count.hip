@@ -37,10 +37,19 @@
 //     A probe that runs off the table marks the range, which is then cleared
 //     and split in halves (depth-first, left half first).
 //
+// Insertion cutoff (s > 1): the members flagged lookup-only (the s - 1
+// longest lists of the item, at most kMaxLookup) walk after the others,
+// behind a barrier, and only add to keys already in the table: a candidate
+// whose overlap reaches s lies in at least one list that inserts it.
+//
 // Two kernels: k_count_small (one wave per item with W_a <= small_max) and
-// k_count_tasks (one workgroup per task group).  Each runs twice: a count pass
-// (pairs per task) and, after the exclusive scan of those counts, a fill pass
-// writing (a, b, w) at the task's offset.
+// k_count_tasks (one workgroup per task group).  Normally one counting pass
+// stages every extracted range's (b, w) in a pool and logs where it goes;
+// after the exclusive scan of the pairs per task, k_stage_copy moves each
+// range to its task's offset, writing (a, b, w).  Tasks that found no room in
+// the pool, or every task when no pool could be had, are counted again in a
+// fill pass that writes at the task's offset directly.  In product mode
+// (`full`, the SpGEMM companion) every b in [0, N) counts, a itself included.
 #include <algorithm>
 
 #include "sline_internal.h"

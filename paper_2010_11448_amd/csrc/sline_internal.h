@@ -209,8 +209,8 @@ hipError_t launch_batch_nnz(hipStream_t st, const BatchGraph *gr, int32_t G, int
                             int32_t *err);
 // XD = rows of the GD dual graphs (graph dual_ids[q] has rows [dbase[q], dbase[q+1])).
 hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32_t *dual_ids,
-                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xrp,
-                               int32_t *xcol, int32_t *xrow, int32_t *err);
+                               const int64_t *dbase, int32_t GD, int64_t E, int32_t *xcol,
+                               int32_t *xrow, int32_t *err);
 // Combined items: graph g owns [ibase[g], ibase[g + 1]); ptrT / colT = XD^T.
 hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                             int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
