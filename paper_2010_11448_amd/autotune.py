@@ -41,15 +41,20 @@ def signature(nnz: Iterable[int], s: Iterable[int], dual: Iterable[int]) -> str:
     return f"nnz2^{int(math.log2(tot))}-g2^{int(math.log2(g))}-s12:{small_s:.1f}-dual:{d:.1f}"
 
 
-def _timed(ctx, run: Callable[[], None], reps: int) -> float:
+def _sync() -> None:
     import torch
 
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+
+
+def _timed(ctx, run: Callable[[], None], reps: int) -> float:
     best = float("inf")
     for _ in range(reps):
-        torch.cuda.synchronize()
+        _sync()
         t0 = time.perf_counter()
         run()
-        torch.cuda.synchronize()
+        _sync()
         best = min(best, time.perf_counter() - t0)
     return best
 
