@@ -188,9 +188,10 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
     uint4 q[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        // a wedge outside the range reads bucket 0 and is ignored below
         b[i] = in[i] ? (int32_t)__umulhi(x[i], R.mul) : 0;
         tag[i] = (x[i] + 1u) << R.cb;
-        q[i] = in[i] ? t4[b[i]] : make_uint4(0u, 0u, 0u, 0u);
+        q[i] = t4[b[i]];
     }
     // first pass: add to a found key, or claim the first free word
     uint32_t addr[4], old[4];
@@ -200,11 +201,13 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
     for (int i = 0; i < 4; ++i) {
         const uint32_t w0 = q[i].x, w1 = q[i].y, w2 = q[i].z, w3 = q[i].w;
         const int32_t used = (w0 != 0u) + (w1 != 0u) + (w2 != 0u) + (w3 != 0u);
+        // same key <=> the words differ only in the count bits (an empty
+        // word never matches: the tag is above the count bits)
         int32_t hit = -1;
-        if (w3 != 0u && (w3 & hmask) == tag[i]) hit = 3;
-        if (w2 != 0u && (w2 & hmask) == tag[i]) hit = 2;
-        if (w1 != 0u && (w1 & hmask) == tag[i]) hit = 1;
-        if (w0 != 0u && (w0 & hmask) == tag[i]) hit = 0;
+        if ((w3 ^ tag[i]) <= R.cmask) hit = 3;
+        if ((w2 ^ tag[i]) <= R.cmask) hit = 2;
+        if ((w1 ^ tag[i]) <= R.cmask) hit = 1;
+        if ((w0 ^ tag[i]) <= R.cmask) hit = 0;
         addr[i] = 4u * (uint32_t)b[i] + (uint32_t)(hit >= 0 ? hit : used);
         old[i] = 0u;
         if (in[i]) {
