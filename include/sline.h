@@ -41,8 +41,12 @@ enum {
 enum {
     SLINE_SKIP_VALIDATE = 1u, /* skip the strictly-increasing row check (range
                                  checks that guard memory always run)       */
-    SLINE_PROFILE = 2u        /* time the stages with HIP events on the
+    SLINE_PROFILE = 2u,       /* time the stages with HIP events on the
                                  context's stream (see sline_stats)          */
+    SLINE_NO_WEIGHTS = 4u     /* pairs only: the w array is neither needed nor
+                                 written (caller buffers may leave w NULL;
+                                 library-allocated results have w = NULL).
+                                 Saves a third of the output traffic.      */
 };
 
 typedef struct sline_ctx sline_ctx;

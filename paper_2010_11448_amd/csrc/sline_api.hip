@@ -67,6 +67,7 @@ struct sline_ctx {
     // stage events (SLINE_PROFILE)
     hipEvent_t ev[8] = {};
     bool profile = false;
+    bool no_weights = false;  // SLINE_NO_WEIGHTS of the current build
     // batch result kept after SLINE_ECAPACITY for an immediate retry
     struct BatchPending {
         bool valid = false;
@@ -161,25 +162,26 @@ void release_pool(sline_ctx *c) {
     c->pool_bytes = 0;
 }
 
-// Staging pool for `want` pairs (8 bytes each), halving on failure; returns
-// the pairs it holds (0: none, count the pairs in a separate pass instead).
-int64_t acquire_pool(sline_ctx *c, int64_t want) {
+// Staging pool for `want` pairs (`pair_bytes` each: 8 with weights, 4
+// without), halving on failure; returns the pairs it holds (0: none, count
+// the pairs in a separate pass instead).
+int64_t acquire_pool(sline_ctx *c, int64_t want, int64_t pair_bytes) {
     release_pool(c);
-    int64_t cap = std::min<int64_t>(want, c->tune.stage_max_bytes / 8);
+    int64_t cap = std::min<int64_t>(want, c->tune.stage_max_bytes / pair_bytes);
     while (cap >= (1 << 20)) {
-        void *p = dev_alloc(c, (size_t)cap * 8);
+        void *p = dev_alloc(c, (size_t)(cap * pair_bytes));
         if (p) {
             c->pool = p;
-            c->pool_bytes = (size_t)cap * 8;
+            c->pool_bytes = (size_t)(cap * pair_bytes);
             return cap;
         }
         cap /= 2;
     }
     if (cap > 0) {
-        void *p = dev_alloc(c, (size_t)cap * 8);
+        void *p = dev_alloc(c, (size_t)(cap * pair_bytes));
         if (p) {
             c->pool = p;
-            c->pool_bytes = (size_t)cap * 8;
+            c->pool_bytes = (size_t)(cap * pair_bytes);
             return cap;
         }
     }
@@ -365,14 +367,15 @@ bool same_call(const sline_ctx::Pending &p, const sline_csr &H, int32_t s, int32
 }
 
 void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
-    int32_t *a = out->a, *b = out->b, *w = out->w;
+    const bool weights = !c->no_weights;
+    int32_t *a = out->a, *b = out->b, *w = weights ? out->w : nullptr;
     bool owned = false;
     if (out->capacity == 0 && total > 0) {
         const size_t bytes = sizeof(int32_t) * (size_t)total;
         a = (int32_t *)dev_alloc(c, bytes);
         b = a ? (int32_t *)dev_alloc(c, bytes) : nullptr;
-        w = b ? (int32_t *)dev_alloc(c, bytes) : nullptr;
-        if (!w) {
+        w = (b && weights) ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+        if (!b || (weights && !w)) {
             dev_free(c, a, bytes);
             dev_free(c, b, bytes);
             set_err(c, "output allocation of %s pairs failed", std::to_string(total).c_str());
@@ -449,8 +452,9 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         set_err(c, "invalid argument (s >= 1, dual in {0,1}, sizes >= 0 required)");
         return SLINE_EINVAL;
     }
-    if (out->capacity < 0 || (out->capacity > 0 && (!out->a || !out->b || !out->w))) {
-        set_err(c, "output buffers: capacity > 0 requires a, b and w");
+    if (out->capacity < 0 ||
+        (out->capacity > 0 && (!out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))))) {
+        set_err(c, "output buffers: capacity > 0 requires a, b and (without SLINE_NO_WEIGHTS) w");
         return SLINE_EINVAL;
     }
     if (same_call(c->pending, H, s, dual, flags)) {
@@ -612,7 +616,9 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const int64_t want_pool = S.wedges / IS.s_min;  // every pair of L_s accounts for >= s wedges
     // the product route counts and fills in two passes (symbolic, then
     // numeric), as SpGEMM does: its product is too large to stage as well
-    const int64_t pool_cap = (want_pool > 0 && !IS.full) ? acquire_pool(c, want_pool) : 0;
+    c->no_weights = (flags & SLINE_NO_WEIGHTS) != 0;
+    const int64_t pool_cap =
+        (want_pool > 0 && !IS.full) ? acquire_pool(c, want_pool, c->no_weights ? 4 : 8) : 0;
     hip_check(c, launch_fill_i32(st, TL.need, T, 0), "zero flags");
     // unused records of a reserved log chunk must read as empty
     hip_check(c, launch_fill_i32(st, reinterpret_cast<int32_t *>(TL.log),
@@ -643,7 +649,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.task_cnt = TL.cnt;
     C.task_off = nullptr;
     C.pool_b = reinterpret_cast<int32_t *>(c->pool);
-    C.pool_w = c->pool ? reinterpret_cast<int32_t *>(c->pool) + pool_cap : nullptr;
+    C.pool_w = (c->pool && !c->no_weights) ? reinterpret_cast<int32_t *>(c->pool) + pool_cap : nullptr;
     C.pool_cap = pool_cap;
     C.pool_head = TL.pool_head;
     C.log = TL.log;
@@ -785,9 +791,9 @@ sline_status batch_split(sline_ctx *c, int32_t G, sline_edges *outs) {
                 const size_t bytes = sizeof(int32_t) * (size_t)need;
                 pa[g] = (int32_t *)dev_alloc(c, bytes);
                 pb[g] = (int32_t *)dev_alloc(c, bytes);
-                pw[g] = (int32_t *)dev_alloc(c, bytes);
+                pw[g] = (P.flags & SLINE_NO_WEIGHTS) ? nullptr : (int32_t *)dev_alloc(c, bytes);
                 owned[g] = 1;
-                if (!pa[g] || !pb[g] || !pw[g]) {
+                if (!pa[g] || !pb[g] || (!pw[g] && !(P.flags & SLINE_NO_WEIGHTS))) {
                     set_err(c, "output allocation failed");
                     throw Fail{SLINE_ENOMEM};
                 }
@@ -845,7 +851,8 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         const sline_csr &H = Hs[g];
         if (s[g] < 1 || (dual[g] != 0 && dual[g] != 1) || H.n_edges < 0 || H.n_vertices < 0 ||
             (H.n_edges > 0 && !H.row_ptr) || outs[g].capacity < 0 ||
-            (outs[g].capacity > 0 && (!outs[g].a || !outs[g].b || !outs[g].w))) {
+            (outs[g].capacity > 0 &&
+             (!outs[g].a || !outs[g].b || (!outs[g].w && !(flags & SLINE_NO_WEIGHTS))))) {
             set_err(c, "invalid arguments for graph %s", std::to_string(g).c_str());
             return SLINE_EINVAL;
         }
@@ -1081,8 +1088,9 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
         set_err(c, "invalid argument (s >= 1, dual in {0,1}, sizes >= 0 required)");
         return SLINE_EINVAL;
     }
-    if (out->capacity < 0 || (out->capacity > 0 && (!out->a || !out->b || !out->w))) {
-        set_err(c, "output buffers: capacity > 0 requires a, b and w");
+    if (out->capacity < 0 ||
+        (out->capacity > 0 && (!out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))))) {
+        set_err(c, "output buffers: capacity > 0 requires a, b and (without SLINE_NO_WEIGHTS) w");
         return SLINE_EINVAL;
     }
     c->pending.valid = false;
@@ -1093,7 +1101,8 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
     sline_edges P{};
     ItemS IS;
     IS.full = true;
-    const sline_status r = build_core(c, H, 1, dual, flags, &P, IS);
+    // the filter reads the product's weights whatever the caller asked for
+    const sline_status r = build_core(c, H, 1, dual, flags & ~(uint32_t)SLINE_NO_WEIGHTS, &P, IS);
     release_pool(c);
     if (r != SLINE_OK) return r;
     sync(c, "product");
@@ -1147,7 +1156,8 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
             set_err(c, "capacity too small");
             return SLINE_ECAPACITY;
         }
-        int32_t *a = out->a, *b = out->b, *w = out->w;
+        int32_t *a = out->a, *b = out->b;
+        int32_t *w = (flags & SLINE_NO_WEIGHTS) ? nullptr : out->w;
         bool owned = false;
         if (out->capacity == 0) {
             a = b = w = nullptr;
@@ -1155,9 +1165,9 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
                 const size_t bytes = sizeof(int32_t) * (size_t)total;
                 a = (int32_t *)dev_alloc(c, bytes);
                 b = (int32_t *)dev_alloc(c, bytes);
-                w = (int32_t *)dev_alloc(c, bytes);
+                w = (flags & SLINE_NO_WEIGHTS) ? nullptr : (int32_t *)dev_alloc(c, bytes);
                 owned = true;
-                if (!a || !b || !w) {
+                if (!a || !b || (!w && !(flags & SLINE_NO_WEIGHTS))) {
                     dev_free(c, a, bytes);
                     dev_free(c, b, bytes);
                     dev_free(c, w, bytes);

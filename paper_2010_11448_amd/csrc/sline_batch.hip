@@ -177,7 +177,7 @@ __global__ void k_batch_split(const int64_t *ibase, const int64_t *off, int32_t 
         const int32_t base = (int32_t)ibase[g];
         oa[g][r] = a[k] - base;
         ob[g][r] = b[k] - base;
-        ow[g][r] = w[k];
+        if (w && ow[g]) ow[g][r] = w[k];
     }
 }
 

@@ -605,7 +605,7 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                     if (ok[k]) {
                         if (dst_a) dst_a[base + pos] = a;
                         dst_b[base + pos] = R.lo + 4 * bk + k;
-                        dst_w[base + pos] = (int32_t)c[k];
+                        if (dst_w) dst_w[base + pos] = (int32_t)c[k];
                         ++pos;
                     }
                 }
@@ -666,7 +666,7 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                         const int32_t p = pos + rank[k];
                         if (dst_a) dst_a[base + p] = a;
                         dst_b[base + p] = R.lo + (int32_t)tag[k] - 1;
-                        dst_w[base + p] = (int32_t)c[k];
+                        if (dst_w) dst_w[base + p] = (int32_t)c[k];
                     }
                 }
                 prev_full = ((fm >> 63) & 1ull) != 0;
@@ -991,7 +991,7 @@ __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) 
         for (int32_t i = lane; i < rec.n; i += kWave) {
             A.out_a[dst + i] = a;
             A.out_b[dst + i] = A.pool_b[rec.off + i];
-            A.out_w[dst + i] = A.pool_w[rec.off + i];
+            if (A.out_w) A.out_w[dst + i] = A.pool_w[rec.off + i];
         }
     }
 }

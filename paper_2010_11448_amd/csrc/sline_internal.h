@@ -171,10 +171,10 @@ struct CountArgs {
     int32_t *queue;              // big-task queue head (reset by the launcher)
     int32_t *task_cnt;           // count mode: pairs per task
     const int64_t *task_off;     // fill mode: output offset per task (nullptr = count mode)
-    int32_t *out_a, *out_b, *out_w;
+    int32_t *out_a, *out_b, *out_w;  // out_w null: weights not written (SLINE_NO_WEIGHTS)
     // stage mode: pool of (b, w) pairs and the range log; tasks that found no
     // room are flagged in need[] (need_count counts them) for a fill pass
-    int32_t *pool_b, *pool_w;
+    int32_t *pool_b, *pool_w;    // pool_w null: weights not staged
     int64_t pool_cap;
     int64_t pool_chunk;          // pool pairs a workgroup reserves at a time
     unsigned long long *pool_head;

@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_product_filter(const int32_t *a, const 
             const int64_t k = t0 + (int64_t)threadIdx.x * PER + i;
             oa[o] = a[k];
             ob[o] = b[k];
-            ow[o] = w[k];
+            if (ow) ow[o] = w[k];
             ++o;
         }
     }

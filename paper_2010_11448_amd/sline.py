@@ -26,6 +26,7 @@ SLINE_EDEVICE = -4
 SLINE_EBUSY = -5
 SLINE_SKIP_VALIDATE = 1
 SLINE_PROFILE = 2
+SLINE_NO_WEIGHTS = 4
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -282,17 +283,19 @@ class Context:
         dev = torch.device("cuda", self.device)
         probe = torch.empty(3, dtype=torch.int32, device=dev)
         out = sline_edges(0, 1, probe[0:1].data_ptr(), probe[1:2].data_ptr(), probe[2:3].data_ptr())
+        nw = bool(flags & SLINE_NO_WEIGHTS)
         st = fn(self.ctx, H, s, dual, flags, ctypes.byref(out))
         if st == SLINE_OK:
             n = int(out.n_pairs)  # 0 or 1 pair: it sits in the probe buffers
-            return LineGraph(probe[0:n].clone(), probe[1:1 + n].clone(), probe[2:2 + n].clone())
+            return LineGraph(probe[0:n].clone(), probe[1:1 + n].clone(),
+                             None if nw else probe[2:2 + n].clone())
         if st != SLINE_ECAPACITY:
             raise SlineError(st, sline_last_error(self.ctx))
         n = int(out.n_pairs)
         a = torch.empty(n, dtype=torch.int32, device=dev)
         b = torch.empty(n, dtype=torch.int32, device=dev)
-        w = torch.empty(n, dtype=torch.int32, device=dev)
-        out = sline_edges(0, n, a.data_ptr(), b.data_ptr(), w.data_ptr())
+        w = None if nw else torch.empty(n, dtype=torch.int32, device=dev)
+        out = sline_edges(0, n, a.data_ptr(), b.data_ptr(), None if nw else w.data_ptr())
         st = fn(self.ctx, H, s, dual, flags, ctypes.byref(out))
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))

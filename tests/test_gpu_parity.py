@@ -238,3 +238,33 @@ def test_tuning_rejects_out_of_range(ctx):
         with pytest.raises(sline.SlineError):
             ctx.set_tuning(**{**base, **bad})
     assert ctx.tuning() == base
+
+
+def test_pairs_only_flag(ctx, dev):
+    """SLINE_NO_WEIGHTS: the same pairs, w neither needed nor written."""
+    import torch
+    from paper_2010_11448_amd import sline
+
+    for g, cases in ((gen.uniform_2000(11), ((1, 0), (2, 1), (3, 0))),
+                     (gen.powerlaw_1m(scale=0.01), ((1, 0), (4, 0), (2, 1)))):
+        rp, col = to_device(g, dev)
+        for s, dual in cases:
+            print(f"case: pairs only s={s} dual={dual}", flush=True)
+            L = ctx.build(rp, col, g.n_vertices, s, dual, sline.SLINE_NO_WEIGHTS)
+            assert L.w is None
+            ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, threads=8)
+            assert np.array_equal(L.a.cpu().numpy(), ref.a) and np.array_equal(L.b.cpu().numpy(), ref.b)
+            Lp = ctx.build(rp, col, g.n_vertices, s, dual, sline.SLINE_NO_WEIGHTS, spgemm=True)
+            assert torch.equal(Lp.a, L.a) and torch.equal(Lp.b, L.b) and Lp.w is None
+    # caller buffers without w
+    g = gen.uniform_2000(12)
+    rp, col = to_device(g, dev)
+    H = sline.Context.csr(rp, col, g.n_vertices)
+    ref, _ = oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, 1)
+    buf = torch.zeros(2 * len(ref), dtype=torch.int32, device=dev)
+    out = sline.sline_edges(0, len(ref), buf[:len(ref)].data_ptr(), buf[len(ref):].data_ptr(), None)
+    assert sline.sline_build(ctx.ctx, H, 1, 0, sline.SLINE_NO_WEIGHTS, out) == sline.SLINE_OK
+    assert np.array_equal(buf[:len(ref)].cpu().numpy(), ref.a)
+    # without the flag a missing w is an error
+    out = sline.sline_edges(0, len(ref), buf[:len(ref)].data_ptr(), buf[len(ref):].data_ptr(), None)
+    assert sline.sline_build(ctx.ctx, H, 1, 0, 0, out) == sline.SLINE_EINVAL
