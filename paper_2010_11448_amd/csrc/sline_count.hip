@@ -62,6 +62,10 @@ constexpr int kR = 8;        // member cursors per thread held in registers
 constexpr int kPiece = 256;  // planned entries per piece of a long member run
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+// Wave index inside the workgroup, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -117,21 +121,31 @@ __device__ __forceinline__ bool too_wide(const Range &R) {
     return R.mul != 0 && (uint64_t)R.span >= (1ull << (32 - R.cb));
 }
 
+// The free word a new key takes in a bucket read as (w0..w3): the first free
+// one going round from word ws; 4 if the bucket is full.
+__device__ __forceinline__ uint32_t free_word(uint32_t ws, uint32_t w0, uint32_t w1, uint32_t w2,
+                                              uint32_t w3) {
+    const uint32_t f = (w0 == 0u ? 1u : 0u) | (w1 == 0u ? 2u : 0u) | (w2 == 0u ? 4u : 0u) |
+                       (w3 == 0u ? 8u : 0u);
+    const uint32_t r = ((f | (f << 4)) >> ws) & 15u;
+    return r ? ((ws + (uint32_t)__builtin_ctz(r)) & 3u) : 4u;
+}
+
 // Hashed insertion of a wedge with key field `tag`, starting at bucket b whose
 // contents were read as q.  Returns false if the probe ran off the table.
-__device__ __forceinline__ bool tab_probe(uint32_t *tab, const Range &R, uint32_t tag, int32_t b,
-                                          uint4 q) {
+__device__ __forceinline__ bool tab_probe(uint32_t *tab, const Range &R, uint32_t tag,
+                                          uint32_t ws, int32_t b, uint4 q) {
     const uint32_t hmask = ~R.cmask;
     const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
     const int32_t nb = R.limit >> 2;
     for (;;) {
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-        int32_t hit = -1, empty = -1;
+        int32_t hit = -1;
 #pragma unroll
-        for (int i = 3; i >= 0; --i) {
+        for (int i = 3; i >= 0; --i)
             if ((w[i] & hmask) == tag) hit = i;
-            if (w[i] == 0u) empty = i;
-        }
+        const uint32_t fw = free_word(ws, q.x, q.y, q.z, q.w);
+        const int32_t empty = fw < 4u ? (int32_t)fw : -1;
         if (hit >= 0) {
             atomicAdd(&tab[4 * b + hit], 1u);
             return true;
@@ -160,11 +174,15 @@ __device__ __forceinline__ uint32_t pick4(int32_t i, uint32_t a0, uint32_t a1, u
 // Count up to four wedges (a candidate >= R.hi means none).  The four home
 // buckets are read together; every wedge that finds its key there is counted
 // with one atomic add and every new key is claimed with one compare-and-swap,
-// all four swaps in flight before any result is looked at.  Buckets fill
-// front to back (a key always takes the first free word), so a bucket's used
-// words are a prefix.  Wedges whose home bucket is full, or whose free word was
-// taken by another key meanwhile, finish in the probe loop (rare at the load
-// factors the range splitting keeps).
+// all four swaps in flight before any result is looked at.  A new key takes
+// the first free word going round from its start word, the quarter of its
+// bucket's share of the range it falls in: neighbouring entries of a sorted
+// list, inserted by neighbouring lanes at once, share a home bucket but
+// mostly not a start word, so their swaps do not collide.  Words never become
+// free again during a pass, so a key is found in its home bucket or, if that
+// bucket was full when it came, in a later one, and a bucket with a free word
+// ends any search.  Wedges whose home bucket is full, or whose free word was
+// taken by another key meanwhile, finish in the probe loop.
 __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t j0, int32_t j1,
                                          int32_t j2, int32_t j3) {
     const int32_t j[4] = {j0, j1, j2, j3};
@@ -184,23 +202,25 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
     const uint32_t hmask = ~R.cmask;
     const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
     int32_t b[4];
-    uint32_t tag[4];
+    uint32_t tag[4], ws[4];
     uint4 q[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         // a wedge outside the range reads bucket 0 and is ignored below
         b[i] = in[i] ? (int32_t)__umulhi(x[i], R.mul) : 0;
+        // where the key lies inside its bucket's share of the range
+        ws[i] = (x[i] * R.mul) >> 30;
         tag[i] = (x[i] + 1u) << R.cb;
         q[i] = t4[b[i]];
     }
-    // first pass: add to a found key, or claim the first free word
+    // first pass: add to a found key, or claim a free word
     uint32_t addr[4], old[4];
     uint32_t pend = 0;  // bit i: wedge i issued a compare-and-swap
     uint32_t slow = 0;  // bit i: wedge i continues in the probe loop
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t w0 = q[i].x, w1 = q[i].y, w2 = q[i].z, w3 = q[i].w;
-        const int32_t used = (w0 != 0u) + (w1 != 0u) + (w2 != 0u) + (w3 != 0u);
+        const uint32_t fw = free_word(ws[i], w0, w1, w2, w3);
         // same key <=> the words differ only in the count bits (an empty
         // word never matches: the tag is above the count bits)
         int32_t hit = -1;
@@ -208,12 +228,12 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
         if ((w2 ^ tag[i]) <= R.cmask) hit = 2;
         if ((w1 ^ tag[i]) <= R.cmask) hit = 1;
         if ((w0 ^ tag[i]) <= R.cmask) hit = 0;
-        addr[i] = 4u * (uint32_t)b[i] + (uint32_t)(hit >= 0 ? hit : used);
+        addr[i] = 4u * (uint32_t)b[i] + (hit >= 0 ? (uint32_t)hit : (fw & 3u));
         old[i] = 0u;
         if (in[i]) {
             if (hit >= 0) {
                 atomicAdd(&tab[addr[i]], 1u);
-            } else if (used < 4) {
+            } else if (fw < 4u) {
                 old[i] = atomicCAS(&tab[addr[i]], 0u, tag[i] | 1u);
                 pend |= 1u << i;
             } else {
@@ -239,10 +259,11 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
         slow &= slow - 1u;
         const int32_t bi = i == 0 ? b[0] : i == 1 ? b[1] : i == 2 ? b[2] : b[3];
         const uint32_t ti = pick4(i, tag[0], tag[1], tag[2], tag[3]);
+        const uint32_t wi = pick4(i, ws[0], ws[1], ws[2], ws[3]);
         if (bi >= nb) {
             ok = false;
         } else {
-            ok &= tab_probe(tab, R, ti, bi, t4[bi]);
+            ok &= tab_probe(tab, R, ti, wi, bi, t4[bi]);
         }
     }
     return ok;
@@ -290,7 +311,7 @@ __device__ __forceinline__ void tab_look4(uint32_t *tab, const Range &R, int32_t
                 break;
             }
             // a bucket with a free word ends the search: the key is absent
-            if (w3 == 0u || ++b[i] >= nb) break;
+            if (w0 == 0u || w1 == 0u || w2 == 0u || w3 == 0u || ++b[i] >= nb) break;
             q[i] = t4[b[i]];
         }
     }
@@ -343,7 +364,7 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
                                              const int32_t (&end)[kR], uint32_t lookm, bool look,
                                              int32_t nend, int32_t (&nc)[kR]) {
     constexpr int W = NT / kWave;
-    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int lane = lane_id(), wid = wave_id();
     const float frac = (float)R.span / (float)((int64_t)nend - R.lo);
     const float light_len = (float)A.tune.light_len;
     bool ok = true;
@@ -407,7 +428,7 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
     // Pieces: each wave keeps four in flight (one 64-entry load each per
     // step), taking pieces h = wid, wid + W, ... in turn.  The entries below
     // R.hi form a prefix of a member's run, so the pieces' counts add up to it.
-    const int32_t npiece = min(S.misc[kMiscRuns], RUNCAP);
+    const int32_t npiece = __builtin_amdgcn_readfirstlane(min(S.misc[kMiscRuns], RUNCAP));
     int32_t next = wid;
     int32_t pr[4], pp[4], pe[4], pg[4];
 #pragma unroll
@@ -419,8 +440,8 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
             if (pr[k] < 0 && next < npiece) {
                 const int2 rr = S.runs[next];
                 pr[k] = next;
-                pp[k] = rr.x;
-                pe[k] = rr.y;
+                pp[k] = __builtin_amdgcn_readfirstlane(rr.x);
+                pe[k] = __builtin_amdgcn_readfirstlane(rr.y);
                 pg[k] = 0;
                 next += W;
             }
@@ -429,8 +450,14 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
         if (!any) break;
         int32_t j[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            j[k] = (pr[k] >= 0 && pp[k] + lane < pe[k]) ? A.itmS[pp[k] + lane] : INT32_MAX;
+        for (int k = 0; k < 4; ++k) {
+            j[k] = INT32_MAX;
+            if (pr[k] >= 0) {
+                // pp < pe while the piece is open: the clamped index is in it
+                const int32_t v = A.itmS[min(pp[k] + lane, pe[k] - 1)];
+                if (pp[k] + lane < pe[k]) j[k] = v;
+            }
+        }
         if (look) tab_look4(S.tab, R, j[0], j[1], j[2], j[3]);
         else ok &= tab_add4(S.tab, R, j[0], j[1], j[2], j[3]);
 #pragma unroll
@@ -487,7 +514,7 @@ template <int NT>
 __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S, const Range &R,
                                                int32_t a, int32_t sa, int32_t t, int64_t rel) {
     constexpr int W = NT / kWave;
-    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int lane = lane_id(), wid = wave_id();
     const int32_t L = R.limit;
     const int32_t nbk = (L + 3) >> 2;  // words past L are zero
     const int32_t per_wave = ((nbk + W * kWave - 1) / (W * kWave)) * kWave;
