@@ -1015,10 +1015,28 @@ __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) 
             if (lane == 0) atomicOr(A.err, kErrInternal);
             continue;
         }
-        for (int32_t i = lane; i < rec.n; i += kWave) {
-            A.out_a[dst + i] = a;
-            A.out_b[dst + i] = A.pool_b[rec.off + i];
-            if (A.out_w) A.out_w[dst + i] = A.pool_w[rec.off + i];
+        // four loads per lane in flight before the stores
+        for (int32_t i0 = 0; i0 < rec.n; i0 += 4 * kWave) {
+            int32_t bv[4], wv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t i = i0 + u * kWave + lane;
+                bv[u] = 0;
+                wv[u] = 0;
+                if (i < rec.n) {
+                    bv[u] = A.pool_b[rec.off + i];
+                    if (A.out_w) wv[u] = A.pool_w[rec.off + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t i = i0 + u * kWave + lane;
+                if (i < rec.n) {
+                    A.out_a[dst + i] = a;
+                    A.out_b[dst + i] = bv[u];
+                    if (A.out_w) A.out_w[dst + i] = wv[u];
+                }
+            }
         }
     }
 }
