@@ -80,6 +80,13 @@ struct sline_ctx {
         size_t bws_bytes = 0;
         int64_t *ibase_dev = nullptr, *off_dev = nullptr;
     } bpend;
+    // a batch whose outputs the library allocates: the fill writes each
+    // graph's pairs straight into its own arrays (G > 0 while such a batch runs)
+    struct Direct {
+        int32_t G = 0;
+        sline_edges *outs = nullptr;
+        bool done = false;  // the fill handed the outputs over
+    } direct;
 };
 
 namespace {
@@ -366,7 +373,124 @@ bool same_call(const sline_ctx::Pending &p, const sline_csr &H, int32_t s, int32
            p.dual == dual && p.flags == flags;
 }
 
+// Launch the fill of a counted build into the outputs set in F (stage copy,
+// or the counting kernels in fill mode) and wait for it.
+void fill_into(sline_ctx *c, CountArgs F) {
+    mark(c, 5);
+    if (c->fill_need >= 0) {
+        // stage mode: move the staged ranges, recompute tasks that found no room
+        hip_check(c, launch_stage_copy(c->stream, F, c->fill_records), "stage copy");
+        if (c->fill_need > 0) {
+            F.mode = kModeFill;
+            hip_check(c, launch_count(c->stream, F), "fill pass (recompute)");
+        }
+    } else {
+        F.mode = kModeFill;
+        F.need = nullptr;
+        hip_check(c, launch_count(c->stream, F), "fill pass");
+    }
+    mark(c, 6);
+    hip_check(c, hipMemcpyAsync(c->host + 8, F.err, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                c->stream),
+              "read flags");
+    sync(c, "fill pass");
+    if (reinterpret_cast<const int32_t *>(c->host + 8)[0] & kErrInternal) {
+        set_err(c, "internal error: inconsistent staged ranges");
+        throw Fail{SLINE_EDEVICE};
+    }
+    if (c->profile) c->stats.ms_fill = span_ms(c, 5, 6);
+}
+
+// Batch with library-allocated outputs: per-graph pair ranges from the task
+// offsets, one allocation per graph, and a fill that writes every pair into
+// its graph's arrays with the graph's item base taken off both ids (no
+// combined result, no split copy).
+void run_fill_direct(sline_ctx *c, int64_t total) {
+    auto &P = c->bpend;
+    const int32_t G = c->direct.G;
+    const bool weights = !c->no_weights;
+    hipStream_t st = c->stream;
+    CountArgs F = c->fill_args;
+    P.off.assign(G + 1, 0);
+    if (total > 0) {
+        hip_check(c, launch_batch_graph_off(st, F.task_item, F.n_tasks, F.task_off, P.ibase_dev, G,
+                                            P.off_dev),
+                  "graph pair offsets");
+        hip_check(c, hipMemcpyAsync(P.off.data(), P.off_dev, sizeof(int64_t) * (G + 1),
+                                    hipMemcpyDeviceToHost, st),
+                  "read graph pair offsets");
+        sync(c, "graph pair offsets");
+        if (P.off[0] != 0 || P.off[G] != total) {
+            set_err(c, "internal error: graph pair offsets do not cover the result");
+            throw Fail{SLINE_EDEVICE};
+        }
+    }
+    std::vector<int32_t *> tab(3 * (size_t)G, nullptr);
+    int32_t **d_tab = nullptr;
+    auto release = [&]() {
+        for (int32_t g = 0; g < G; ++g) {
+            const size_t bytes = sizeof(int32_t) * (size_t)(P.off[g + 1] - P.off[g]);
+            dev_free(c, tab[g], bytes);
+            dev_free(c, tab[G + g], bytes);
+            dev_free(c, tab[2 * G + g], bytes);
+        }
+        dev_free(c, d_tab, sizeof(int32_t *) * tab.size());
+    };
+    try {
+        for (int32_t g = 0; g < G; ++g) {
+            const int64_t need = P.off[g + 1] - P.off[g];
+            if (need < 0) {
+                set_err(c, "internal error: graph pair offsets out of order");
+                throw Fail{SLINE_EDEVICE};
+            }
+            if (need == 0) continue;
+            const size_t bytes = sizeof(int32_t) * (size_t)need;
+            tab[g] = (int32_t *)dev_alloc(c, bytes);
+            tab[G + g] = (int32_t *)dev_alloc(c, bytes);
+            tab[2 * G + g] = weights ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+            if (!tab[g] || !tab[G + g] || (weights && !tab[2 * G + g])) {
+                set_err(c, "output allocation for graph %s failed", std::to_string(g).c_str());
+                throw Fail{SLINE_ENOMEM};
+            }
+        }
+        if (total > 0) {
+            d_tab = (int32_t **)dev_alloc(c, sizeof(int32_t *) * tab.size());
+            if (!d_tab) {
+                set_err(c, "output table allocation failed");
+                throw Fail{SLINE_ENOMEM};
+            }
+            hip_check(c, hipMemcpyAsync(d_tab, tab.data(), sizeof(int32_t *) * tab.size(),
+                                        hipMemcpyHostToDevice, st),
+                      "upload output table");
+            F.out_a = F.out_b = F.out_w = nullptr;
+            F.n_graphs = G;
+            F.g_ibase = P.ibase_dev;
+            F.g_off = P.off_dev;
+            F.g_out = d_tab;
+            fill_into(c, F);  // waits for the stream: the table upload is done too
+            dev_free(c, d_tab, sizeof(int32_t *) * tab.size());
+            d_tab = nullptr;
+        }
+    } catch (...) {
+        release();
+        throw;
+    }
+    for (int32_t g = 0; g < G; ++g) {
+        sline_edges &o = c->direct.outs[g];
+        o.n_pairs = P.off[g + 1] - P.off[g];
+        o.a = tab[g];
+        o.b = tab[G + g];
+        o.w = tab[2 * G + g];
+    }
+    c->direct.done = true;
+}
+
 void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
+    if (c->direct.G > 0) {
+        run_fill_direct(c, total);
+        out->n_pairs = total;
+        return;
+    }
     const bool weights = !c->no_weights;
     int32_t *a = out->a, *b = out->b, *w = weights ? out->w : nullptr;
     bool owned = false;
@@ -389,29 +513,7 @@ void run_fill(sline_ctx *c, sline_edges *out, int64_t total) {
         F.out_b = b;
         F.out_w = w;
         try {
-            mark(c, 5);
-            if (c->fill_need >= 0) {
-                // stage mode: move the staged ranges, recompute tasks that found no room
-                hip_check(c, launch_stage_copy(c->stream, F, c->fill_records), "stage copy");
-                if (c->fill_need > 0) {
-                    F.mode = kModeFill;
-                    hip_check(c, launch_count(c->stream, F), "fill pass (recompute)");
-                }
-            } else {
-                F.mode = kModeFill;
-                F.need = nullptr;
-                hip_check(c, launch_count(c->stream, F), "fill pass");
-            }
-            mark(c, 6);
-            hip_check(c, hipMemcpyAsync(c->host + 8, F.err, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                        c->stream),
-                      "read flags");
-            sync(c, "fill pass");
-            if (reinterpret_cast<const int32_t *>(c->host + 8)[0] & kErrInternal) {
-                set_err(c, "internal error: inconsistent staged ranges");
-                throw Fail{SLINE_EDEVICE};
-            }
-            if (c->profile) c->stats.ms_fill = span_ms(c, 5, 6);
+            fill_into(c, F);
         } catch (...) {
             if (owned) {
                 const size_t bytes = sizeof(int32_t) * (size_t)total;
@@ -1037,8 +1139,27 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         IS.item_end = iend;
         IS.s_min = s_min;
         IS.s_max = s_max;
+        // library-allocated outputs of several graphs: the fill writes them
+        // directly (one graph takes the combined arrays as they are)
+        bool direct = G > 1;
+        for (int32_t g = 0; g < G; ++g) direct = direct && outs[g].capacity == 0;
+        struct DirectScope {
+            sline_ctx *c;
+            ~DirectScope() { c->direct = sline_ctx::Direct{}; }
+        } scope{c};
+        if (direct) {
+            for (int32_t g = 0; g < G; ++g) outs[g] = sline_edges{};
+            c->direct.G = G;
+            c->direct.outs = outs;
+        }
         const sline_status r =
             build_core(c, CH, s_min, 0, flags | SLINE_SKIP_VALIDATE, &comb, IS);
+        if (r == SLINE_OK && c->direct.done) {
+            release_pool(c);
+            dev_free(c, big, big_bytes);
+            drop_batch_pending(c);
+            return SLINE_OK;
+        }
         if (r != SLINE_OK) {
             dev_free(c, big, big_bytes);
             drop_batch_pending(c);
@@ -1268,9 +1389,11 @@ sline_status sline_build(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uin
         return build_impl(c, H, s, dual, flags, out);
     } catch (const Fail &f) {
         c->pending.valid = false;
+        release_pool(c);
         return f.st;
     } catch (const std::bad_alloc &) {
         c->pending.valid = false;
+        release_pool(c);
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;
     }
@@ -1290,10 +1413,12 @@ sline_status sline_build_batch(sline_ctx *c, int32_t n_graphs, const sline_csr *
     } catch (const Fail &f) {
         drop_batch_pending(c);
         c->pending.valid = false;
+        release_pool(c);
         return f.st;
     } catch (const std::bad_alloc &) {
         drop_batch_pending(c);
         c->pending.valid = false;
+        release_pool(c);
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;
     }

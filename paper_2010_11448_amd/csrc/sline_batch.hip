@@ -181,7 +181,31 @@ __global__ void k_batch_split(const int64_t *ibase, const int64_t *off, int32_t 
     }
 }
 
+// One thread per graph boundary g = 0..G: the first pair of graph g.
+__global__ void k_batch_graph_off(const int32_t *task_item, int32_t T, const int64_t *task_off,
+                                  const int64_t *g_ibase, int32_t G, int64_t *g_off) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > G) return;
+    const int64_t first = g_ibase[g];
+    int32_t lo = 0, hi = T;  // first task with task_item >= first
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if ((int64_t)task_item[mid] < first) lo = mid + 1;
+        else hi = mid;
+    }
+    g_off[g] = task_off[lo];
+}
+
 }  // namespace
+
+hipError_t launch_batch_graph_off(hipStream_t st, const int32_t *task_item, int32_t n_tasks,
+                                  const int64_t *task_off, const int64_t *g_ibase, int32_t G,
+                                  int64_t *g_off) {
+    if (G <= 0) return hipSuccess;
+    k_batch_graph_off<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(task_item, n_tasks, task_off,
+                                                                     g_ibase, G, g_off);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_nnz(hipStream_t st, const BatchGraph *gr, int32_t G, int64_t *nnz,
                             int32_t *err) {

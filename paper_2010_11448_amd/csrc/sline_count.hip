@@ -485,6 +485,34 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
     }
 }
 
+// Where the pairs of item `item` at combined output position `pos` go: the
+// single output, or (batches written per graph) the arrays of the item's
+// graph at the position inside it, ids to be written less `shift`.
+struct OutDst {
+    int32_t *a, *b, *w;
+    int64_t base;
+    int32_t shift;
+};
+
+__device__ __forceinline__ OutDst out_dst(const CountArgs &A, int32_t item, int64_t pos) {
+    OutDst d{A.out_a, A.out_b, A.out_w, pos, 0};
+    const int32_t G = A.n_graphs;
+    if (G > 0) {
+        int32_t lo = 0, hi = G;  // g_ibase[lo] <= item < g_ibase[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (A.g_ibase[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        d.a = A.g_out[lo];
+        d.b = A.g_out[G + lo];
+        d.w = A.g_out[2 * G + lo];
+        d.base = pos - A.g_off[lo];
+        d.shift = (int32_t)A.g_ibase[lo];
+    }
+    return d;
+}
+
 // Zero table words [0, limit); `tab` is 16-byte aligned.
 template <int NT>
 __device__ __forceinline__ void tab_clear(uint32_t *tab, int32_t limit) {
@@ -541,13 +569,16 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
     }
     bool write = false;
     int64_t base = 0;
+    int32_t shift = 0;  // fill mode, batches written per graph: the graph's item base
     int32_t *dst_a = nullptr, *dst_b = nullptr, *dst_w = nullptr;
     if (total && A.mode == kModeFill) {
         write = true;
-        base = A.task_off[t] + rel;
-        dst_a = A.out_a;
-        dst_b = A.out_b;
-        dst_w = A.out_w;
+        const OutDst od = out_dst(A, a, A.task_off[t] + rel);
+        base = od.base;
+        shift = od.shift;
+        dst_a = od.a;
+        dst_b = od.b;
+        dst_w = od.w;
     } else if (total && A.mode == kModeStage) {
         if (threadIdx.x == 0) {
             // Pool room and log slots come from chunks this workgroup reserved
@@ -630,8 +661,8 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (ok[k]) {
-                        if (dst_a) dst_a[base + pos] = a;
-                        dst_b[base + pos] = R.lo + 4 * bk + k;
+                        if (dst_a) dst_a[base + pos] = a - shift;
+                        dst_b[base + pos] = R.lo + 4 * bk + k - shift;
                         if (dst_w) dst_w[base + pos] = (int32_t)c[k];
                         ++pos;
                     }
@@ -691,8 +722,8 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                 for (int k = 0; k < 4; ++k) {
                     if (ok[k]) {
                         const int32_t p = pos + rank[k];
-                        if (dst_a) dst_a[base + p] = a;
-                        dst_b[base + p] = R.lo + (int32_t)tag[k] - 1;
+                        if (dst_a) dst_a[base + p] = a - shift;
+                        dst_b[base + p] = R.lo + (int32_t)tag[k] - 1 - shift;
                         if (dst_w) dst_w[base + p] = (int32_t)c[k];
                     }
                 }
@@ -1015,6 +1046,7 @@ __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) 
             if (lane == 0) atomicOr(A.err, kErrInternal);
             continue;
         }
+        const OutDst od = out_dst(A, a, dst);
         // four loads per lane in flight before the stores
         for (int32_t i0 = 0; i0 < rec.n; i0 += 4 * kWave) {
             int32_t bv[4], wv[4];
@@ -1025,16 +1057,16 @@ __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) 
                 wv[u] = 0;
                 if (i < rec.n) {
                     bv[u] = A.pool_b[rec.off + i];
-                    if (A.out_w) wv[u] = A.pool_w[rec.off + i];
+                    if (od.w) wv[u] = A.pool_w[rec.off + i];
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int32_t i = i0 + u * kWave + lane;
                 if (i < rec.n) {
-                    A.out_a[dst + i] = a;
-                    A.out_b[dst + i] = bv[u];
-                    if (A.out_w) A.out_w[dst + i] = wv[u];
+                    od.a[od.base + i] = a - od.shift;
+                    od.b[od.base + i] = bv[u] - od.shift;
+                    if (od.w) od.w[od.base + i] = wv[u];
                 }
             }
         }

@@ -189,6 +189,14 @@ struct CountArgs {
     int32_t *err;
     Tuning tune;
     int32_t n_cu;
+    // batches written straight to per-graph outputs (n_graphs > 0; fill and
+    // stage-copy writes only): graph g owns the combined items
+    // [g_ibase[g], g_ibase[g + 1]) and the pairs [g_off[g], g_off[g + 1]); its
+    // arrays are g_out[g], g_out[G + g] and g_out[2G + g] (null without
+    // weights), and both ids are written less g_ibase[g]
+    int32_t n_graphs;
+    const int64_t *g_ibase, *g_off;
+    int32_t *const *g_out;
 };
 // `mid` (may be null) is recorded between the one-wave kernel and the task kernel.
 hipError_t launch_count(hipStream_t st, const CountArgs &a, hipEvent_t mid = nullptr);
@@ -223,6 +231,12 @@ hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, 
 hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,
                               const int32_t *a, const int32_t *b, const int32_t *w, int64_t P,
                               int32_t *const *oa, int32_t *const *ob, int32_t *const *ow);
+
+// g_off[g] = task_off of the first task whose item is >= g_ibase[g], for
+// g = 0..G (task_item is non-decreasing; task_off has n_tasks + 1 entries).
+hipError_t launch_batch_graph_off(hipStream_t st, const int32_t *task_item, int32_t n_tasks,
+                                  const int64_t *task_off, const int64_t *g_ibase, int32_t G,
+                                  int64_t *g_off);
 
 // Copy staged ranges to their final place (skipping tasks flagged in need).
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);

@@ -51,9 +51,15 @@ struct Graph {
 // Device memory of the workers (and of handed-over results): large chunks
 // from hipMalloc, carved into blocks by best fit and merged again on release,
 // so the serving loop maps device memory once instead of per query (mapping
-// fresh memory costs more than most builds).  When no chunk has room and
-// hipMalloc fails, chunks with nothing allocated are returned and the request
-// is retried.
+// fresh memory costs more than most builds).  A chunk is only requested when
+// the device reports the memory free: a hipMalloc that fails for lack of
+// memory can take seconds, during which no worker could allocate.  (The
+// budget itself is kept by admission, which lets a query larger than the
+// budget run alone.)  When no chunk has room,
+// chunks with nothing allocated are returned first; if that does not make
+// room the request fails at once and the library takes its fallback (a
+// smaller staging pool, or an error the worker answers by running the
+// batch's queries apart).
 struct DeviceCache {
     struct Chunk {
         char *base = nullptr;
@@ -64,6 +70,10 @@ struct DeviceCache {
     std::vector<Chunk *> chunks;
     std::map<void *, std::pair<Chunk *, size_t>> live;  // block -> (chunk, length)
     size_t chunk_min = (size_t)4 << 30;
+    size_t total = 0;                           // bytes the chunks add up to
+    static constexpr size_t kHeadroom = (size_t)1 << 30;  // left free on the device
+    // device calls made so far (reported by the server log)
+    int64_t n_malloc = 0, n_malloc_fail = 0, n_free = 0, ns_malloc = 0, ns_free = 0;
 
     static size_t round(size_t n) {
         const size_t g = (size_t)2 << 20;
@@ -90,22 +100,45 @@ struct DeviceCache {
         return p;
     }
 
+    // bytes a new chunk for a request of n bytes may have (0: the device
+    // has not that much free)
+    size_t grow_size(size_t n) const {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        const size_t avail = fr > kHeadroom ? fr - kHeadroom : 0;
+        if (n > avail) return 0;
+        return std::min(std::max(n, chunk_min), avail);
+    }
+
     void *alloc(size_t n) {
         n = round(n);
         std::lock_guard<std::mutex> lk(mu);
         if (void *p = carve(n)) return p;
         for (int attempt = 0; attempt < 2; ++attempt) {
-            const size_t sz = std::max(n, chunk_min);
+            const size_t sz = grow_size(n);
+            if (sz == 0) {
+                if (attempt == 0 && release_empty()) continue;
+                return nullptr;
+            }
             void *base = nullptr;
-            if (hipMalloc(&base, sz) == hipSuccess) {
+            const int64_t t0 = now_ns();
+            const hipError_t e = hipMalloc(&base, sz);
+            ns_malloc += now_ns() - t0;
+            ++n_malloc;
+            if (e == hipSuccess) {
                 Chunk *c = new Chunk();
                 c->base = static_cast<char *>(base);
                 c->size = sz;
                 c->free[0] = sz;
                 chunks.push_back(c);
+                total += sz;
                 return carve(n);
             }
             (void)hipGetLastError();
+            ++n_malloc_fail;
             if (attempt == 0) release_empty();
         }
         return nullptr;
@@ -137,18 +170,25 @@ struct DeviceCache {
         c->free[off] = len;
     }
 
-    // caller holds mu
-    void release_empty() {
+    // caller holds mu; returns whether a chunk was freed
+    bool release_empty() {
         std::vector<Chunk *> keep;
+        bool freed = false;
         for (Chunk *c : chunks) {
             if (c->used == 0) {
+                freed = true;
+                total -= c->size;
+                const int64_t t0 = now_ns();
                 (void)hipFree(c->base);
+                ns_free += now_ns() - t0;
+                ++n_free;
                 delete c;
             } else {
                 keep.push_back(c);
             }
         }
         chunks.swap(keep);
+        return freed;
     }
 
     void destroy() {
@@ -159,6 +199,7 @@ struct DeviceCache {
         }
         chunks.clear();
         live.clear();
+        total = 0;
     }
 };
 
@@ -260,27 +301,70 @@ void worker_loop(sline_server *S, int wi) {
                 q.worker = wi;
             }
         }
+        int64_t c0[5] = {0, 0, 0, 0, 0};
+        if (S->log) {
+            std::lock_guard<std::mutex> lk(S->cache.mu);
+            c0[0] = S->cache.n_malloc;
+            c0[1] = S->cache.n_malloc_fail;
+            c0[2] = S->cache.n_free;
+            c0[3] = S->cache.ns_malloc;
+            c0[4] = S->cache.ns_free;
+        }
         const int64_t t_run = now_ns();
-        const sline_status st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), 0, outs.data());
+        const uint32_t flags = S->log ? SLINE_PROFILE : 0;
+        sline_status st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), flags,
+                                            outs.data());
+        // per query: the batch's status, or its own when the batch ran apart
+        std::vector<sline_status> qst(G, st);
+        const bool apart = st == SLINE_ENOMEM && G > 1;
+        if (apart) {
+            // device memory ran short for the batch as a whole: run its
+            // queries one at a time (a single graph needs no combined output)
+            for (int32_t g = 0; g < G; ++g) {
+                outs[g] = sline_edges{};
+                qst[g] = sline_build_batch(W.ctx, 1, &Hs[g], &ss[g], &ds[g], flags, &outs[g]);
+            }
+            st = SLINE_OK;
+            for (int32_t g = 0; g < G; ++g)
+                if (qst[g] != SLINE_OK) st = qst[g];
+        }
         const int64_t t_done = now_ns();
         if (S->log) {
             int64_t pairs = 0, big = 0;
             for (int32_t g = 0; g < G; ++g) {
-                pairs += st == SLINE_OK ? outs[g].n_pairs : 0;
+                pairs += qst[g] == SLINE_OK ? outs[g].n_pairs : 0;
                 big += Hs[g].n_edges >= 500000;
             }
-            fprintf(stderr, "sline-server: worker %d batch of %d (%lld large, est %.2f GB) status %d "
-                    "pairs %lld %.1f ms\n", wi, G, (long long)big, est / 1e9, st, (long long)pairs,
-                    (t_done - t_run) / 1e6);
+            sline_stats ps{};
+            (void)sline_last_stats(W.ctx, &ps);
+            int64_t c1[5];
+            size_t cache_bytes = 0;
+            {
+                std::lock_guard<std::mutex> lk(S->cache.mu);
+                cache_bytes = S->cache.total;
+                c1[0] = S->cache.n_malloc;
+                c1[1] = S->cache.n_malloc_fail;
+                c1[2] = S->cache.n_free;
+                c1[3] = S->cache.ns_malloc;
+                c1[4] = S->cache.ns_free;
+            }
+            // cache figures are process-wide: they include other workers' calls meanwhile
+            fprintf(stderr, "sline-server: worker %d batch of %d%s (%lld large, est %.2f GB) status %d "
+                    "pairs %lld %.1f ms [transpose %.1f prepare %.1f count %.1f fill %.1f; "
+                    "hipMalloc %lld (%lld failed) %.1f ms, hipFree %lld %.1f ms, cache %.1f GB]\n",
+                    wi, G, apart ? " run apart" : "", (long long)big, est / 1e9, st, (long long)pairs, (t_done - t_run) / 1e6,
+                    ps.ms_transpose, ps.ms_prepare, ps.ms_count, ps.ms_fill,
+                    (long long)(c1[0] - c0[0]), (long long)(c1[1] - c0[1]), (c1[3] - c0[3]) / 1e6,
+                    (long long)(c1[2] - c0[2]), (c1[4] - c0[4]) / 1e6, cache_bytes / 1e9);
         }
         std::string err = st == SLINE_OK ? std::string() : std::string(sline_last_error(W.ctx));
         {
             std::lock_guard<std::mutex> lk(S->mu);
             for (int32_t g = 0; g < G; ++g) {
                 Query &q = S->queries[batch[g]];
-                q.info.status = st;
+                q.info.status = qst[g];
                 q.info.t_done_ns = t_done;
-                if (st == SLINE_OK) {
+                if (qst[g] == SLINE_OK) {
                     q.out = outs[g];
                     q.info.n_pairs = outs[g].n_pairs;
                 }

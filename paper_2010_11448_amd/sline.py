@@ -301,10 +301,61 @@ class Context:
             raise SlineError(st, sline_last_error(self.ctx))
         return LineGraph(a, b, w)
 
-    def build_batch(self, graphs, s, dual=None, flags: int = 0) -> list[LineGraph]:
-        """L_{s[g]} of every graph (row_ptr, col, n_vertices) in one batched call."""
+    def build_owned(self, row_ptr, col, n_vertices: int, s: int, dual: int = 0,
+                    flags: int = 0) -> sline_edges:
+        """One sline_build call whose output the library allocates (capacity 0);
+        release it with ``free_edges([out])``."""
+        out = sline_edges()
+        st = sline_build(self.ctx, self.csr(row_ptr, col, n_vertices), s, dual, flags, out)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return out
+
+    def build_batch_owned(self, graphs, s, dual=None, flags: int = 0):
+        """One sline_build_batch call whose outputs the library allocates
+        (capacity 0): returns the ``sline_edges`` array; release every entry
+        with ``free_edges``."""
+        G = len(graphs)
+        dual = [0] * G if dual is None else list(dual)
+        csrs = [self.csr(rp, col, n) for rp, col, n in graphs]
+        outs = (sline_edges * max(G, 1))()
+        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return outs
+
+    def free_edges(self, outs, n: int | None = None) -> None:
+        for g in range(len(outs) if n is None else n):
+            sline_edges_free(self.ctx, outs[g])
+
+    def build_batch(self, graphs, s, dual=None, flags: int = 0,
+                    library_alloc: bool = False) -> list[LineGraph]:
+        """L_{s[g]} of every graph (row_ptr, col, n_vertices) in one batched call.
+
+        library_alloc=True lets the library allocate the outputs (the results
+        are copied into torch tensors and the library's arrays released)."""
         import torch
         G = len(graphs)
+        if library_alloc:
+            outs = self.build_batch_owned(graphs, s, dual, flags)
+            dev = torch.device("cuda", self.device)
+            nw = bool(flags & SLINE_NO_WEIGHTS)
+
+            def col(ptr, n, weights):
+                if weights and nw:
+                    return None
+                if n == 0 or not ptr:
+                    return torch.empty(0, dtype=torch.int32, device=dev)
+                return torch.as_tensor(_DeviceArray(ptr, n), device=dev).clone()
+
+            res = []
+            for g in range(G):
+                n = int(outs[g].n_pairs)
+                res.append(LineGraph(col(outs[g].a, n, False), col(outs[g].b, n, False),
+                                     col(outs[g].w, n, True)))
+            torch.cuda.synchronize(dev)
+            self.free_edges(outs, G)
+            return res
         dual = [0] * G if dual is None else list(dual)
         csrs = [self.csr(rp, col, n) for rp, col, n in graphs]
         dev = torch.device("cuda", self.device)

@@ -6,6 +6,7 @@ and the plain single-graph build of the same graph.
 
 from __future__ import annotations
 
+import numpy as np
 import pytest
 
 import oracle
@@ -71,6 +72,43 @@ def test_batch_matches_oracle_and_plain(ctx, dev, seed):
         rp, col = dg[g]
         alone = ctx.build(rp, col, h.n_vertices, s, d)
         assert_same(alone, ref, f"alone graph {g}")
+
+
+@pytest.mark.parametrize("pool", ["default", "small", "none"])
+def test_batch_library_outputs(ctx, dev, pool):
+    """Library-allocated outputs: each graph's pairs are written straight into
+    its own arrays, by the staged copy, by the fill pass over tasks the pool
+    had no room for ("small"), or by a fill pass over every task ("none")."""
+    graphs, ss, duals = _mixed_batch(20, 5)
+    dg = [to_device(h, dev) for h in graphs]
+    base = ctx.tuning()
+    stage = {"default": base["stage_max_bytes"], "small": 1 << 20, "none": 0}[pool]
+    print(f"case: batch library outputs pool={pool} s={ss} dual={duals}", flush=True)
+    ctx.set_tuning(stage_max_bytes=stage)
+    try:
+        res = ctx.build_batch([(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)], ss,
+                              duals, library_alloc=True)
+    finally:
+        ctx.set_tuning(**base)
+    assert len(res) == len(graphs)
+    for g, (h, s, d) in enumerate(zip(graphs, ss, duals)):
+        ref, _ = oracle.naive(h.row_ptr, h.col, h.n_edges, h.n_vertices, s, dual=d, threads=8)
+        assert_same(res[g], ref, f"library outputs pool={pool} graph {g} s={s} dual={d}")
+
+
+def test_batch_library_outputs_pairs_only(ctx, dev):
+    from paper_2010_11448_amd import sline
+
+    graphs, ss, duals = _mixed_batch(12, 6)
+    dg = [to_device(h, dev) for h in graphs]
+    print(f"case: batch library outputs pairs only s={ss} dual={duals}", flush=True)
+    res = ctx.build_batch([(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)], ss, duals,
+                          flags=sline.SLINE_NO_WEIGHTS, library_alloc=True)
+    for g, (h, s, d) in enumerate(zip(graphs, ss, duals)):
+        ref, _ = oracle.naive(h.row_ptr, h.col, h.n_edges, h.n_vertices, s, dual=d, threads=8)
+        assert res[g].w is None
+        assert np.array_equal(res[g].a.cpu().numpy(), ref.a), f"graph {g}: a"
+        assert np.array_equal(res[g].b.cpu().numpy(), ref.b), f"graph {g}: b"
 
 
 def test_batch_of_law_graphs_against_wedge_oracle(ctx, dev):
