@@ -215,7 +215,9 @@ struct Layout {
     int64_t *totals, *passes;
     int32_t *rowid, *degT, *ptrT, *fillT, *colT, *mid_list, *big_list;
     int32_t *kT = nullptr, *posT = nullptr;  // transposed position <-> incidence
-    int32_t *ptrS, *cntS, *itmS;
+    int32_t *ptrS, *itmS;
+    int32_t *pos;   // s filter: kept entries before each member-list entry (nnz + 1)
+    int32_t *xcol;  // batches: columns of the dual graphs' rows (XD)
     int64_t *cost, *tbase, *part64;
     int32_t *part32, *ntask, *start;
 };
@@ -237,12 +239,12 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
     L.posT = A.take<int32_t>(nnz);
     L.mid_list = A.take<int32_t>(n);
     L.big_list = A.take<int32_t>(n);
-    const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m}) + 1);
+    const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m, nnz}) + 1);
     L.part32 = A.take<int32_t>(pmax);
     L.part64 = A.take<int64_t>(pmax);
     if (filt) {
         L.ptrS = A.take<int32_t>(M + 1);
-        L.cntS = A.take<int32_t>(M);
+        L.pos = A.take<int32_t>(nnz + 1);
         L.itmS = A.take<int32_t>(nnz);
     }
     L.cost = A.take<int64_t>(N);
@@ -670,13 +672,9 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     // 5. s filter
     const int32_t *ptrS = ptrM, *itmS = itmM;
     if (filt) {
-        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, IS.s_item, nullptr, L.cntS,
-                                   nullptr),
-                  "filter count");
-        hip_check(c, launch_scan_i32(st, L.cntS, M, L.ptrS, L.part32), "filter scan");
-        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, ptrI, s, IS.s_item, L.ptrS, L.cntS,
-                                   L.itmS, inv, L.start),
-                  "filter fill");
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, nnz, ptrI, s, IS.s_item, L.pos,
+                                   L.part32, L.ptrS, L.itmS, inv, L.start),
+                  "filter");
         ptrS = L.ptrS;
         itmS = L.itmS;
     }
@@ -985,7 +983,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         s_max = std::max(s_max, s[g]);
     }
     // small workspace: descriptors, nnz, flags, item bases, pair offsets, dual lists
-    const size_t small = sizeof(BatchGraph) * G + 8 * (size_t)(4 * G + 16) + 4096;
+    const size_t small = sizeof(BatchGraph) * G + 8 * (size_t)(5 * G + 16) + 4096;
     P.bws_bytes = small;
     P.bws = dev_alloc(c, small);
     if (!P.bws) {
@@ -1001,6 +999,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     P.off_dev = W.take<int64_t>(G + 1);
     int64_t *d_dbase = W.take<int64_t>(G + 1);
     int32_t *d_dual_ids = W.take<int32_t>(G);
+    int32_t *d_zb = W.take<int32_t>(G + 1);
     hip_check(c, launch_fill_i32(st, d_err, 4, 0), "zero flags");
     hip_check(c, hipMemcpyAsync(d_gr, gr.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, st),
               "upload graphs");
@@ -1084,7 +1083,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         memC = A.take<int32_t>(ZT);
         s_item = A.take<int32_t>(NI);
         iend = A.take<int32_t>(NI);
-        X.cntS = A.take<int32_t>(ZD);  // XD columns
+        X.xcol = A.take<int32_t>(ZD);
     };
     Layout X{};
     int32_t *len, *ptrC, *memC, *s_item, *iend;
@@ -1101,7 +1100,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         Arena A;
         A.base = reinterpret_cast<char *>(big);
         plan(A, X, len, ptrC, memC, s_item, iend);
-        int32_t *xcol = X.cntS;
+        int32_t *xcol = X.xcol;
         hip_check(c, launch_fill_i32(st, xcol, ZD, 0), "zero dual columns");
         hip_check(c, launch_fill_i32(st, X.rowid, ZD, 0), "zero dual rows");
         if (GD > 0 && E > 0) {
@@ -1117,7 +1116,7 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         hip_check(c, launch_batch_len(st, d_gr, P.ibase_dev, G, NI, X.ptrT, len, s_item, iend, d_err),
                   "item lengths");
         hip_check(c, launch_scan_i32(st, len, NI, ptrC, X.part32), "item scan");
-        hip_check(c, launch_batch_rows(st, d_gr, P.ibase_dev, G, NI, X.ptrT, X.colT, ptrC, memC, d_err),
+        hip_check(c, launch_batch_rows(st, d_gr, P.ibase_dev, G, ZT, X.ptrT, X.colT, ptrC, d_zb, memC),
                   "item rows");
         hip_check(c, hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
                   "read flags");

@@ -105,6 +105,16 @@ __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t 
             if (b < 0 || en < b || en > d.nnz) {
                 atomicOr(err, kErrRowPtrOrder);
                 l = 0;
+            } else {
+                // members in range and strictly increasing
+                int32_t bad = 0, prev = -1;
+                for (int32_t k = b; k < en; ++k) {
+                    const int32_t v = d.col[k];
+                    if (v < 0 || v >= d.n) bad |= kErrColRange;
+                    if (v <= prev) bad |= kErrColOrder;
+                    prev = v;
+                }
+                if (bad) atomicOr(err, bad);
             }
         }
         len[i] = l;
@@ -113,34 +123,35 @@ __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t 
     }
 }
 
-// One wave per combined item: copy its members into the combined CSR with
-// the graph's member base (primal rows are checked here).
-__global__ __launch_bounds__(256) void k_batch_rows(const BatchGraph *gr, const int64_t *ibase,
-                                                    int32_t G, int64_t NI, const int32_t *ptrT,
-                                                    const int32_t *colT, const int32_t *ptrC,
-                                                    int32_t *memC, int32_t *err) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t i = wave; i < NI; i += nwaves) {
-        const int32_t g = find_graph(ibase, G, i);
-        const BatchGraph d = gr[g];
-        const int32_t loc = (int32_t)(i - ibase[g]);
-        const int32_t o = ptrC[i], l = ptrC[i + 1] - o;
+// First combined incidence of every graph: zb[g] = ptrC[ibase[g]], g = 0..G.
+__global__ void k_batch_zbase(const int64_t *ibase, int32_t G, const int32_t *ptrC, int32_t *zb) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= G) zb[g] = ptrC[ibase[g]];
+}
+
+// One thread per combined incidence z (grid-stride).  Graph g's incidences
+// are the contiguous range [zb[g], zb[g + 1]) in graph order: a primal
+// graph's are its col array (rows checked by k_batch_len), shifted to the
+// combined member ids; a dual graph's are its block of XD^T (rows of its
+// vertices), whose entries are combined row ids of XD turned into member ids.
+__global__ void k_batch_rows(const BatchGraph *gr, const int32_t *zb, int32_t G, int64_t ZT,
+                             const int32_t *ptrT, const int32_t *colT, int32_t *memC) {
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < ZT;
+         z += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = G;  // zb[lo] <= z < zb[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if ((int64_t)zb[mid] <= z) lo = mid;
+            else hi = mid;
+        }
+        const BatchGraph d = gr[lo];
+        const int64_t k = z - zb[lo];
         if (d.dual) {
-            const int32_t src = ptrT[d.vdbase + loc];
-            for (int32_t k = lane; k < l; k += kWave)
-                memC[o + k] = (int32_t)(colT[src + k] - d.dbase + d.mbase);
+            memC[z] = (int32_t)(colT[ptrT[d.vdbase] + k] - d.dbase + d.mbase);
         } else {
-            const int32_t src = d.rp[loc];
-            int32_t bad = 0;
-            for (int32_t k = lane; k < l; k += kWave) {
-                const int32_t v = d.col[src + k];
-                if (v < 0 || v >= d.n) bad |= kErrColRange;
-                if (k > 0 && d.col[src + k - 1] >= v) bad |= kErrColOrder;
-                memC[o + k] = (v >= 0 && v < d.n) ? (int32_t)(d.mbase + v) : (int32_t)d.mbase;
-            }
-            if (bad) atomicOr(err, bad);
+            // a malformed graph (reported by k_batch_len) may map past its col
+            const int32_t v = k < d.nnz ? d.col[k] : -1;
+            memC[z] = (v >= 0 && v < d.n) ? (int32_t)(d.mbase + v) : (int32_t)d.mbase;
         }
     }
 }
@@ -233,11 +244,13 @@ hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t 
 }
 
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
-                             int64_t NI, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *memC, int32_t *err) {
-    if (NI <= 0) return hipSuccess;
-    k_batch_rows<<<grid_for(NI * kWave, 256, 65536), 256, 0, st>>>(gr, ibase, G, NI, ptrT, colT,
-                                                                   ptrC, memC, err);
+                             int64_t ZT, const int32_t *ptrT, const int32_t *colT,
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC) {
+    if (G <= 0) return hipSuccess;
+    k_batch_zbase<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(ibase, G, ptrC, zb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ZT <= 0) return e;
+    k_batch_rows<<<grid_for(ZT, 256, 65536), 256, 0, st>>>(gr, zb, G, ZT, ptrT, colT, memC);
     return hipGetLastError();
 }
 

@@ -86,15 +86,17 @@ hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t
 hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
                                     int32_t *dst);
 
-// Filtered membership lists N_s(v): the items b of v's list with size >=
-// s (s_item[b] when s_item is given: every item carries its own s).  With
-// start given, pass 2 also writes the back-pointer of every kept entry:
-// start[inv[k]] = (its position in itmS) + 1, inv mapping member-list
+// s filter: N_s(v) = the items of N(v) with |S| >= s (s_item[it] for item it
+// when s_item is given), every list in its order, written to itmS with list
+// pointers ptrS (M + 1 entries).  pos (nnz + 1 entries) receives the kept
+// entries before each member-list entry; part32 holds the scan's partials.
+// With start given, the back-pointer of every kept entry is written as well:
+// start[inv[p]] = (its position in itmS) + 1, inv mapping member-list
 // positions to item incidences.
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
-                         int32_t *cntS, int32_t *itmS, const int32_t *inv = nullptr,
-                         int32_t *start = nullptr);
+                         int64_t nnz, const int32_t *ptrI, int32_t s, const int32_t *s_item,
+                         int32_t *pos, int32_t *part32, int32_t *ptrS, int32_t *itmS,
+                         const int32_t *inv, int32_t *start);
 
 // Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
 // in N_s(v) for member incidence k of a kept item a) and the run totals:
@@ -223,9 +225,11 @@ hipError_t launch_batch_concat(hipStream_t st, const BatchGraph *gr, const int32
 hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                             int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
                             int32_t *item_end, int32_t *err);
+// Combined member lists: zb (G + 1 entries) receives each graph's first
+// combined incidence; memC[ZT] the member ids (one thread per incidence).
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
-                             int64_t NI, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *memC, int32_t *err);
+                             int64_t ZT, const int32_t *ptrT, const int32_t *colT,
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC);
 hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, const int32_t *a,
                                int64_t P, int64_t *off);
 hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,

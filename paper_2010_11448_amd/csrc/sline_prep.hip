@@ -327,38 +327,37 @@ __global__ void k_bitonic_step(int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
 
 // -------------------------------------------------------- s filtering
 
-// One wave per member list (grid-stride).  Pass 1 (itmS == nullptr) counts
-// the items of size >= s (s_item[b] for item b when given); pass 2 writes
-// them, in list order, at ptrS[v].
-__global__ __launch_bounds__(256) void k_filter(const int32_t *ptrM, const int32_t *itmM,
-                                                int32_t M, const int32_t *ptrI, int32_t s,
-                                                const int32_t *s_item, const int32_t *ptrS,
-                                                int32_t *cntS, int32_t *itmS, const int32_t *inv,
-                                                int32_t *start) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t v = wave; v < M; v += nwaves) {
-        const int32_t b = ptrM[v], e = ptrM[v + 1];
-        int32_t run = itmS ? ptrS[v] : 0;
-        for (int32_t k0 = b; k0 < e; k0 += kWave) {
-            const int32_t k = k0 + lane;
-            bool keep = false;
-            int32_t it = 0;
-            if (k < e) {
-                it = itmM[k];
-                keep = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s);
+// The s filter as a stream compaction: the filtered lists N_s(v), one after
+// the other, are the kept entries of the member lists in their order, so the
+// position of a kept entry is the number of kept entries before it.
+// keep[p] = 1 if entry p of the member lists is an item with |S| >= s
+// (s_item[it] for item it when given).
+__global__ void k_filter_flags(const int32_t *itmM, int64_t nnz, const int32_t *ptrI, int32_t s,
+                               const int32_t *s_item, int32_t *keep) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t it = itmM[p];
+        keep[p] = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s) ? 1 : 0;
+    }
+}
+
+// After the exclusive scan of the flags (pos[p], pos[nnz] = kept total): kept
+// entry p goes to itmS[pos[p]], and the item's own entry sets its
+// back-pointer start[inv[p]] to the position after it; ptrS[v] = pos[ptrM[v]].
+__global__ void k_filter_scatter(const int32_t *itmM, int64_t nnz, const int32_t *pos,
+                                 const int32_t *ptrM, int32_t M, int32_t *ptrS, int32_t *itmS,
+                                 const int32_t *inv, int32_t *start) {
+    const int64_t n = nnz > (int64_t)M + 1 ? nnz : (int64_t)M + 1;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (p < nnz) {
+            const int32_t q = pos[p];
+            if (pos[p + 1] != q) {
+                itmS[q] = itmM[p];
+                if (start) start[inv[p]] = q + 1;
             }
-            const uint64_t bal = __ballot(keep);
-            if (itmS && keep) {
-                const int32_t q = run + (int32_t)lanes_below(bal);
-                itmS[q] = it;
-                // the kept item's own entry: its walk over v starts just after it
-                if (start) start[inv[k]] = q + 1;
-            }
-            run += __popcll(bal);
         }
-        if (!itmS && lane == 0) cntS[v] = run;
+        if (p <= M) ptrS[p] = pos[ptrM[p]];
     }
 }
 
@@ -634,11 +633,20 @@ hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t 
 }
 
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         const int32_t *ptrI, int32_t s, const int32_t *s_item, const int32_t *ptrS,
-                         int32_t *cntS, int32_t *itmS, const int32_t *inv, int32_t *start) {
+                         int64_t nnz, const int32_t *ptrI, int32_t s, const int32_t *s_item,
+                         int32_t *pos, int32_t *part32, int32_t *ptrS, int32_t *itmS,
+                         const int32_t *inv, int32_t *start) {
     if (M <= 0) return hipSuccess;
-    k_filter<<<grid_for((int64_t)M * kWave, 256, 65536), 256, 0, st>>>(
-        ptrM, itmM, M, ptrI, s, s_item, ptrS, cntS, itmS, inv, start);
+    if (nnz > 0) {
+        k_filter_flags<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(itmM, nnz, ptrI, s, s_item, pos);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // in place: every scan thread reads its inputs before writing them
+    hipError_t e = launch_scan_i32(st, pos, nnz, pos, part32);
+    if (e != hipSuccess) return e;
+    k_filter_scatter<<<grid_for(std::max<int64_t>(nnz, (int64_t)M + 1), 256, 65536), 256, 0, st>>>(
+        itmM, nnz, pos, ptrM, M, ptrS, itmS, inv, start);
     return hipGetLastError();
 }
 
