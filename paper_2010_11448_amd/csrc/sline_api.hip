@@ -211,9 +211,10 @@ double span_ms(sline_ctx *c, int i, int j) {
 }
 
 struct Layout {
-    int32_t *err, *seg, *queue, *tcounts;
+    int32_t *err, *queue, *tcounts;
     int64_t *totals, *passes;
-    int32_t *rowid, *degT, *ptrT, *fillT, *colT, *mid_list, *big_list;
+    int32_t *rowid, *ptrT, *colT;
+    int32_t *rsK0, *rsK1, *rsV0, *rsV1, *rsHist;  // transpose (radix sort) buffers
     int32_t *kT = nullptr, *posT = nullptr;  // transposed position <-> incidence
     int32_t *ptrS, *itmS;
     int32_t *pos;   // s filter: kept entries before each member-list entry (nnz + 1)
@@ -225,20 +226,20 @@ struct Layout {
 Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64_t M, bool filt) {
     Layout L{};
     L.err = A.take<int32_t>(4);
-    L.seg = A.take<int32_t>(4);
     L.queue = A.take<int32_t>(4);
     L.tcounts = A.take<int32_t>(4);
     L.totals = A.take<int64_t>(4);
     L.passes = A.take<int64_t>(4);
     L.rowid = A.take<int32_t>(nnz);
-    L.degT = A.take<int32_t>(n);
     L.ptrT = A.take<int32_t>(n + 1);
-    L.fillT = A.take<int32_t>(n);
     L.colT = A.take<int32_t>(nnz);
     L.kT = A.take<int32_t>(nnz);
     L.posT = A.take<int32_t>(nnz);
-    L.mid_list = A.take<int32_t>(n);
-    L.big_list = A.take<int32_t>(n);
+    L.rsK0 = A.take<int32_t>(nnz);
+    L.rsK1 = A.take<int32_t>(nnz);
+    L.rsV0 = A.take<int32_t>(nnz);
+    L.rsV1 = A.take<int32_t>(nnz);
+    L.rsHist = A.take<int32_t>(16 * transpose_tiles(nnz) + 1);
     const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m, nnz}) + 1);
     L.part32 = A.take<int32_t>(pmax);
     L.part64 = A.take<int64_t>(pmax);
@@ -298,74 +299,11 @@ void ensure_ws2(sline_ctx *c, size_t bytes) {
 }
 
 void transpose(sline_ctx *c, const Layout &L, const int32_t *col, int32_t n, int64_t nnz) {
-    hipStream_t st = c->stream;
-    hip_check(c, launch_fill_i32(st, L.degT, n, 0), "zero degrees");
-    hip_check(c, launch_fill_i32(st, L.fillT, n, 0), "zero cursors");
-    hip_check(c, launch_degree(st, col, nnz, n, L.degT), "degree");
-    hip_check(c, launch_scan_i32(st, L.degT, n, L.ptrT, L.part32), "transpose scan");
-    hip_check(c, launch_scatter(st, col, L.rowid, nnz, n, L.ptrT, L.fillT, L.colT), "scatter");
-    hip_check(c, launch_segsort_classify(st, L.ptrT, n, L.mid_list, L.big_list, L.seg), "classify rows");
-    hip_check(c, launch_segsort_small(st, L.ptrT, n, L.colT), "sort short rows");
-    hip_check(c, launch_segsort_mid(st, L.ptrT, L.mid_list, L.seg, std::max(1, c->n_cu * 8), L.colT),
-              "sort rows in LDS");
-    hip_check(c, hipMemcpyAsync(c->host, L.seg, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-              "read row classes");
-    sync(c, "transpose");
-    const int32_t *hs = reinterpret_cast<const int32_t *>(c->host);
-    const int32_t nbig = hs[1], maxdeg = hs[2];
-    if (nbig == 0) {
-        hip_check(c, launch_transpose_fix(st, nnz, L.rowid, L.colT, L.kT, L.posT), "transpose fix");
-        return;
-    }
-    // rows longer than the LDS sort: bitonic network in global memory, one row at a time
-    int32_t n2 = 1;
-    while (n2 < maxdeg) n2 <<= 1;
-    int32_t *big = (int32_t *)malloc(sizeof(int32_t) * (size_t)nbig);
-    int32_t *bptr = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)nbig);
-    if (!big || !bptr) {
-        free(big);
-        free(bptr);
-        set_err(c, "host allocation failed");
-        throw Fail{SLINE_ENOMEM};
-    }
-    int32_t *tmp = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)n2);
-    if (!tmp) {
-        free(big);
-        free(bptr);
-        set_err(c, "device allocation failed (long-row sort)");
-        throw Fail{SLINE_ENOMEM};
-    }
-    try {
-        hip_check(c, hipMemcpyAsync(big, L.big_list, sizeof(int32_t) * nbig, hipMemcpyDeviceToHost, st),
-                  "read long rows");
-        sync(c, "read long rows");
-        for (int32_t q = 0; q < nbig; ++q) {
-            hip_check(c, hipMemcpyAsync(bptr + 2 * q, L.ptrT + big[q], 2 * sizeof(int32_t),
-                                        hipMemcpyDeviceToHost, st),
-                      "read long row bounds");
-        }
-        sync(c, "read long row bounds");
-        for (int32_t q = 0; q < nbig; ++q) {
-            const int32_t b = bptr[2 * q], len = bptr[2 * q + 1] - b;
-            int32_t m2 = 1;
-            while (m2 < len) m2 <<= 1;
-            hip_check(c, launch_segsort_big_load(st, L.colT + b, len, m2, tmp), "long row load");
-            for (int32_t k = 2; k <= m2; k <<= 1)
-                for (int32_t j = k >> 1; j > 0; j >>= 1)
-                    hip_check(c, launch_bitonic_step(st, tmp, m2, k, j), "long row sort");
-            hip_check(c, launch_segsort_big_store(st, tmp, len, L.colT + b), "long row store");
-        }
-        sync(c, "long row sort");
-        hip_check(c, launch_transpose_fix(st, nnz, L.rowid, L.colT, L.kT, L.posT), "transpose fix");
-    } catch (...) {
-        dev_free(c, tmp, sizeof(int32_t) * (size_t)n2);
-        free(big);
-        free(bptr);
-        throw;
-    }
-    dev_free(c, tmp, sizeof(int32_t) * (size_t)n2);
-    free(big);
-    free(bptr);
+    int32_t *const rk[2] = {L.rsK0, L.rsK1};
+    int32_t *const rv[2] = {L.rsV0, L.rsV1};
+    hip_check(c, launch_transpose(c->stream, col, nnz, n, L.rowid, rk, rv, L.rsHist, L.part32,
+                                  L.ptrT, L.colT, L.kT, L.posT),
+              "transpose");
 }
 
 bool same_call(const sline_ctx::Pending &p, const sline_csr &H, int32_t s, int32_t dual,
@@ -642,7 +580,6 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const Layout L = plan_layout(A, m, n, nnz, N, M, filt);
 
     hip_check(c, launch_fill_i32(st, L.err, 4, 0), "zero flags");
-    hip_check(c, launch_fill_i32(st, L.seg, 4, 0), "zero classes");
     hip_check(c, launch_fill_i32(st, L.tcounts, 4, 0), "zero task counts");
     hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
     hip_check(c, launch_fill_i64(st, L.passes, 4, 0), "zero passes");
@@ -1071,13 +1008,13 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
                     int32_t *&memC, int32_t *&s_item, int32_t *&iend) {
         X.rowid = A.take<int32_t>(ZD);
         X.colT = A.take<int32_t>(ZD);
-        X.degT = A.take<int32_t>(VD);
         X.ptrT = A.take<int32_t>(VD + 1);
-        X.fillT = A.take<int32_t>(VD);
-        X.mid_list = A.take<int32_t>(VD);
-        X.big_list = A.take<int32_t>(VD);
-        X.seg = A.take<int32_t>(4);
-        X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>(VD, NI) + 1));
+        X.rsK0 = A.take<int32_t>(ZD);
+        X.rsK1 = A.take<int32_t>(ZD);
+        X.rsV0 = A.take<int32_t>(ZD);
+        X.rsV1 = A.take<int32_t>(ZD);
+        X.rsHist = A.take<int32_t>(16 * transpose_tiles(ZD) + 1);
+        X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>({VD, NI, ZD}) + 1));
         len = A.take<int32_t>(NI);
         ptrC = A.take<int32_t>(NI + 1);
         memC = A.take<int32_t>(ZT);
@@ -1107,7 +1044,6 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
             hip_check(c, launch_batch_concat(st, d_gr, d_dual_ids, d_dbase, GD, E, xcol, X.rowid,
                                              d_err),
                       "dual rows");
-            hip_check(c, launch_fill_i32(st, X.seg, 4, 0), "zero classes");
             if (ZD > 0) transpose(c, X, xcol, (int32_t)VD, ZD);
             else hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
         } else if (VD > 0) {

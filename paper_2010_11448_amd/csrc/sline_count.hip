@@ -67,6 +67,12 @@ __device__ __forceinline__ int wave_id() {
     return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
+__device__ __forceinline__ int32_t wave_total(int32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -999,26 +1005,76 @@ __global__ void k_task_count(const int64_t *cost, int32_t N, int32_t small_max, 
 }
 
 // counts[0] small tasks, counts[1] task groups
-__global__ void k_task_fill(const int64_t *cost, int32_t N, int32_t small_max, int32_t target,
-                            int32_t group, const int64_t *tbase, int32_t *task_item,
-                            int32_t *task_part, int32_t *small_tasks, int32_t *groups,
-                            int32_t *counts) {
-    for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
-         a += (int64_t)gridDim.x * blockDim.x) {
+// Each workgroup fills the tasks of a contiguous chunk of items.  The slots
+// of the two lists are claimed with one global atomic per list and workgroup
+// (same-address atomics serialize), then handed out inside the workgroup
+// with LDS atomics, one per wave and step.
+__global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t N,
+                                                   int32_t small_max, int32_t target,
+                                                   int32_t group, const int64_t *tbase,
+                                                   int32_t *task_item, int32_t *task_part,
+                                                   int32_t *small_tasks, int32_t *groups,
+                                                   int32_t *counts, int32_t chunk) {
+    __shared__ int32_t sh[2];
+    const int lane = lane_id();
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < N ? lo + chunk : N;
+    if (threadIdx.x == 0) sh[0] = sh[1] = 0;
+    __syncthreads();
+    // pass 1: list entries of the chunk
+    int32_t ns = 0, ng = 0;
+    for (int64_t a = lo + threadIdx.x; a < hi; a += blockDim.x) {
         const int64_t c = cost[a];
         const int32_t P = task_parts(c, small_max, target);
         if (P == 0) continue;
-        const int64_t t0 = tbase[a];
+        if (c <= small_max) ++ns;
+        else ng += (P + group - 1) / group;
+    }
+    ns = wave_total(ns);
+    ng = wave_total(ng);
+    if (lane == 0) {
+        if (ns) atomicAdd(&sh[0], ns);
+        if (ng) atomicAdd(&sh[1], ng);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sh[0] = sh[0] ? atomicAdd(&counts[0], sh[0]) : 0;
+        sh[1] = sh[1] ? atomicAdd(&counts[1], sh[1]) : 0;
+    }
+    __syncthreads();
+    // pass 2: tasks, and the list entries at the claimed slots
+    for (int64_t base = lo + (threadIdx.x & ~(kWave - 1)); base < hi; base += blockDim.x) {
+        const int64_t a = base + lane;
+        int64_t c = 0;
+        int32_t P = 0;
+        int64_t t0 = 0;
+        if (a < hi) {
+            c = cost[a];
+            P = task_parts(c, small_max, target);
+            if (P > 0) t0 = tbase[a];
+        }
         for (int32_t p = 0; p < P; ++p) {
             task_item[t0 + p] = (int32_t)a;
             task_part[t0 + p] = p;
         }
-        if (c <= small_max) {
-            small_tasks[atomicAdd(&counts[0], 1)] = (int32_t)t0;
-            continue;
+        const bool small = P > 0 && c <= small_max;
+        const int32_t G = (P > 0 && !small) ? (P + group - 1) / group : 0;
+        const uint64_t sm = __ballot(small);
+        int32_t sbase = 0;
+        if (lane == 0 && sm) sbase = atomicAdd(&sh[0], (int32_t)__popcll(sm));
+        sbase = __shfl(sbase, 0, kWave);
+        if (small) small_tasks[sbase + (int32_t)lanes_below(sm)] = (int32_t)t0;
+        int32_t incl = G;  // inclusive prefix of G over the wave
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int32_t u = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += u;
         }
-        const int32_t G = (P + group - 1) / group;
-        const int32_t at = atomicAdd(&counts[1], G);
+        const int32_t tot = __shfl(incl, kWave - 1, kWave);
+        int32_t gbase = 0;
+        if (lane == kWave - 1 && tot) gbase = atomicAdd(&sh[1], tot);
+        gbase = __shfl(gbase, kWave - 1, kWave);
+        const int32_t at = gbase + incl - G;
         for (int32_t g = 0; g < G; ++g) groups[at + g] = (int32_t)(t0 + (int64_t)g * group);
     }
 }
@@ -1092,10 +1148,12 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *big_tasks, int32_t *counts) {
     if (N <= 0) return hipSuccess;
-    k_task_fill<<<grid_for(N, 256, 65536), 256, 0, st>>>(cost, N, tu.small_max_wedges,
-                                                        tu.task_wedges, std::max(1, tu.group_parts),
-                                                        tbase, task_item, task_part, small_tasks,
-                                                        big_tasks, counts);
+    const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
+    const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
+    const int64_t grid = ((int64_t)N + chunk - 1) / chunk;
+    k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges,
+                                                std::max(1, tu.group_parts), tbase, task_item,
+                                                task_part, small_tasks, big_tasks, counts, chunk);
     return hipGetLastError();
 }
 

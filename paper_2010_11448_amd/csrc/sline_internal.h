@@ -35,10 +35,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// Transposed rows up to this many entries are sorted in LDS.
-constexpr int kSegSortLds = 16384;
-constexpr int kSegSortSmall = 32;
-
 // Table sizes (home slots) of the counting kernels.
 constexpr int kSmallSlots = 1024;
 constexpr int kTaskSlots = 8960;  // + 64 pad: 9024 packed 4-byte slots, four workgroups per CU
@@ -50,8 +46,7 @@ constexpr int kTaskThreads = 256;
 hipError_t launch_check_rowptr(hipStream_t st, const int32_t *rp, int32_t m, int32_t *err);
 hipError_t launch_rows(hipStream_t st, const int32_t *rp, const int32_t *col, int32_t m,
                        int32_t n, int64_t nnz, int check_order, int32_t *rowid, int32_t *err);
-hipError_t launch_degree(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
-                         int32_t *deg);
+
 hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v);
 hipError_t launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
 hipError_t launch_copy_i32(hipStream_t st, int32_t *dst, const int32_t *src, int64_t n);
@@ -64,27 +59,21 @@ hipError_t launch_scan_i32(hipStream_t st, const int32_t *in, int64_t n, int32_t
 hipError_t launch_scan_i32_to_i64(hipStream_t st, const int32_t *in, int64_t n, int64_t *out,
                                   int64_t *partial);
 
-// colT receives incidence indices (sorted per row like row ids); after the
-// sorts launch_transpose_fix turns them into row ids and records the maps
-// kT (transposed position -> incidence) and posT (incidence -> position).
-hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *rowid, int64_t nnz,
-                          int32_t n, const int32_t *ptrT, int32_t *fill, int32_t *colT);
-hipError_t launch_transpose_fix(hipStream_t st, int64_t nnz, const int32_t *rowid, int32_t *colT,
-                                int32_t *kT, int32_t *posT);
 // start[k] = map[k] + 1 (unfiltered member lists)
 hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map, int32_t *start);
-// Sorts every transposed row ascending.  `counts` holds 3 int32 (mid, big,
-// max degree), `mid_list`/`big_list` hold up to n entries each.
-hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
-                                   int32_t *mid_list, int32_t *big_list, int32_t *counts);
-hipError_t launch_segsort_small(hipStream_t st, const int32_t *ptr, int32_t n, int32_t *val);
-hipError_t launch_segsort_mid(hipStream_t st, const int32_t *ptr, const int32_t *mid_list,
-                              const int32_t *counts, int32_t grid, int32_t *val);
-hipError_t launch_segsort_big_load(hipStream_t st, const int32_t *src, int32_t len, int32_t n2,
-                                   int32_t *tmp);
-hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t k, int32_t j);
-hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
-                                    int32_t *dst);
+
+// Transpose of an nnz-entry CSR with members in [0, n): ptrT (n + 1), colT
+// (the item rowid[k] of each incidence, grouped by member, items ascending),
+// kT[q] = the incidence at transposed slot q and posT[k] = its slot (kT,
+// posT may be null).  A stable least-significant-digit radix sort of the
+// (member, incidence) pairs; rsK / rsV are two pairs of nnz-entry buffers,
+// hist holds 16 * transpose_tiles(nnz) + 1 counts and part32 the partials of
+// their scan.
+int64_t transpose_tiles(int64_t nnz);
+hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
+                            const int32_t *rowid, int32_t *const rsK[2], int32_t *const rsV[2],
+                            int32_t *hist, int32_t *part32, int32_t *ptrT, int32_t *colT,
+                            int32_t *kT, int32_t *posT);
 
 // s filter: N_s(v) = the items of N(v) with |S| >= s (s_item[it] for item it
 // when s_item is given), every list in its order, written to itmS with list

@@ -112,13 +112,6 @@ __global__ __launch_bounds__(256) void k_rows(const int32_t *rp, const int32_t *
     if (bad) atomicOr(err, bad);
 }
 
-__global__ void k_degree(const int32_t *col, int64_t nnz, int32_t n, int32_t *deg) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v = col[k];
-        if (v >= 0 && v < n) atomicAdd(&deg[v], 1);
-    }
-}
 
 template <typename T>
 __global__ void k_fill(T *p, int64_t n, T v) {
@@ -204,30 +197,7 @@ __global__ void k_zero_total(TO *out) { out[0] = 0; }
 
 // ---------------------------------------------------------- transpose
 
-__global__ void k_scatter(const int32_t *col, const int32_t *rowid, int64_t nnz, int32_t n,
-                          const int32_t *ptrT, int32_t *fill, int32_t *colT) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int32_t v = col[k];
-        if (v < 0 || v >= n) continue;
-        int32_t p = ptrT[v] + atomicAdd(&fill[v], 1);
-        colT[p] = (int32_t)k;  // incidence index: within a row it orders like the row id
-    }
-}
 
-// After the per-row sort of incidence indices: colT[p] becomes the row id of
-// incidence kT[p] = colT[p], and posT[k] the transposed position of incidence
-// k (kT / posT may be null).
-__global__ void k_transpose_fix(int64_t nnz, const int32_t *rowid, int32_t *colT, int32_t *kT,
-                                int32_t *posT) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = colT[p];
-        if (kT) kT[p] = k;
-        if (posT) posT[k] = (int32_t)p;
-        colT[p] = rowid[k];
-    }
-}
 
 // start[k] = map[k] + 1 for every item incidence k (lists not filtered: the
 // first item after a in N(v) follows a's own position in the list).
@@ -237,91 +207,137 @@ __global__ void k_start_from_map(int64_t nnz, const int32_t *map, int32_t *start
         start[k] = map[k] + 1;
 }
 
-__global__ void k_segsort_classify(const int32_t *ptr, int32_t n, int32_t *mid_list,
-                                   int32_t *big_list, int32_t *counts) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        int32_t d = ptr[v + 1] - ptr[v];
-        if (d > kSegSortSmall && d <= kSegSortLds) mid_list[atomicAdd(&counts[0], 1)] = (int32_t)v;
-        else if (d > kSegSortLds) {
-            big_list[atomicAdd(&counts[1], 1)] = (int32_t)v;
-            atomicMax(&counts[2], d);
+
+
+
+
+
+// ------------------------------------------------ transpose by radix sort
+// The transpose is a stable sort of the incidences (v = col[k], k) by member
+// v: least significant digit first, kRsBits bits per pass.  A pass counts
+// the digits of each tile of kRsTile keys (k_rs_hist), scans the counts
+// bin by bin across tiles, and moves every key to its bin's place
+// (k_rs_scatter).  Inside a tile, thread t holds kRsItems consecutive keys
+// and counts them per bin in its own LDS counters; a block scan of the
+// counters in (bin, thread) order gives every key its place, so equal
+// digits keep their order within the tile, and the bin-major offsets keep
+// the order of the tiles.
+constexpr int kRsBits = 4;
+constexpr int kRsBins = 1 << kRsBits;
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+// Digit counts of each tile, bin-major: hist[bin * ntiles + tile].
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const int32_t *keys, int64_t n, int shift,
+                                                        int32_t *hist, int32_t ntiles) {
+    __shared__ int32_t h[kRsBins];
+    if (threadIdx.x < kRsBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    int32_t mine = 0;  // lane b < kRsBins: this wave's count of digit b
+    for (int i = threadIdx.x & ~(kWave - 1); i < kRsTile; i += kRsThreads) {
+        const int64_t p = base + i + lane;
+        const int32_t d = p < n ? (int32_t)(((uint32_t)keys[p] >> shift) & (kRsBins - 1)) : -1;
+#pragma unroll
+        for (int b = 0; b < kRsBins; ++b) {
+            const int32_t cb = (int32_t)__popcll(__ballot(d == b));
+            if (lane == b) mine += cb;
+        }
+    }
+    if (lane < kRsBins && mine) atomicAdd(&h[lane], mine);
+    __syncthreads();
+    if (threadIdx.x < kRsBins) hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Move the keys of each tile to their place: off[bin * ntiles + tile] is the
+// first output slot of the tile's keys with that digit.  vin null: the value
+// of key p is p.  The last pass writes, instead of the values, the final
+// maps: kT[q] = value (the incidence), colT[q] = rowid[value] (its item),
+// posT[value] = q (kT, posT may be null).
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(
+    const int32_t *kin, const int32_t *vin, int64_t n, int shift, const int32_t *off,
+    int32_t ntiles, int32_t *kout, int32_t *vout, int32_t last, const int32_t *rowid,
+    int32_t *colT, int32_t *kT, int32_t *posT) {
+    __shared__ int32_t cnt[kRsBins * kRsThreads];  // [bin][thread]
+    __shared__ int32_t sk[kRsTile], sv[kRsTile];   // the tile in sorted order
+    __shared__ int32_t sh[kRsThreads / kWave + 1];
+    __shared__ int32_t bin_start[kRsBins];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)t * kRsItems;
+    int32_t key[kRsItems], val[kRsItems], dig[kRsItems];
+#pragma unroll
+    for (int b = 0; b < kRsBins; ++b) cnt[b * kRsThreads + t] = 0;
+#pragma unroll
+    for (int i = 0; i < kRsItems; ++i) {
+        const int64_t p = base + i;
+        dig[i] = -1;
+        if (p < n) {
+            key[i] = kin[p];
+            val[i] = vin ? vin[p] : (int32_t)p;
+            dig[i] = (int32_t)(((uint32_t)key[i] >> shift) & (kRsBins - 1));
+            cnt[dig[i] * kRsThreads + t] += 1;
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counters in (bin, thread) order: thread t takes
+    // entries [t * kRsBins, (t + 1) * kRsBins) of the flattened array
+    int32_t loc[kRsBins];
+    int32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kRsBins; ++j) {
+        loc[j] = cnt[t * kRsBins + j];
+        sum += loc[j];
+    }
+    int32_t total;
+    int32_t run = block_excl_scan<int32_t>(sum, sh, total);
+#pragma unroll
+    for (int j = 0; j < kRsBins; ++j) {
+        cnt[t * kRsBins + j] = run;
+        run += loc[j];
+    }
+    __syncthreads();
+    if (t < kRsBins) bin_start[t] = cnt[t * kRsThreads];
+    __syncthreads();
+    // place the keys in tile order, then write each bin's run with
+    // consecutive lanes
+#pragma unroll
+    for (int i = 0; i < kRsItems; ++i) {
+        if (dig[i] < 0) continue;
+        const int32_t r = cnt[dig[i] * kRsThreads + t]++;
+        sk[r] = key[i];
+        sv[r] = val[i];
+    }
+    __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+    const int32_t tn = (int32_t)(n - tile0 < kRsTile ? n - tile0 : kRsTile);
+    for (int32_t j = t; j < tn; j += kRsThreads) {
+        const int32_t k = sk[j], v = sv[j];
+        const int32_t b = (int32_t)(((uint32_t)k >> shift) & (kRsBins - 1));
+        const int32_t q = off[b * ntiles + blockIdx.x] + (j - bin_start[b]);
+        kout[q] = k;
+        if (!last) {
+            vout[q] = v;
+        } else {
+            if (kT) kT[q] = v;
+            if (posT) posT[v] = q;
+            colT[q] = rowid[v];
         }
     }
 }
 
-// Rows of up to kSegSortSmall entries: one thread, insertion sort in place.
-__global__ void k_segsort_small(const int32_t *ptr, int32_t n, int32_t *val) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t b = ptr[v], d = ptr[v + 1] - b;
-        if (d < 2 || d > kSegSortSmall) continue;
-        int32_t *x = val + b;
-        for (int32_t i = 1; i < d; ++i) {
-            int32_t key = x[i];
-            int32_t j = i - 1;
-            while (j >= 0 && x[j] > key) {
-                x[j + 1] = x[j];
-                --j;
-            }
-            x[j + 1] = key;
-        }
-    }
-}
-
-// Rows of kSegSortSmall < d <= kSegSortLds entries: one workgroup, bitonic
-// sort in LDS padded to a power of two.
-__global__ __launch_bounds__(256) void k_segsort_mid(const int32_t *ptr, const int32_t *mid_list,
-                                                     const int32_t *counts, int32_t *val) {
-    __shared__ int32_t buf[kSegSortLds];
-    const int32_t nmid = counts[0];
-    for (int32_t r = blockIdx.x; r < nmid; r += gridDim.x) {
-        const int32_t v = mid_list[r];
-        const int32_t b = ptr[v], d = ptr[v + 1] - b;
-        int32_t n2 = 1;
-        while (n2 < d) n2 <<= 1;
-        for (int32_t i = threadIdx.x; i < n2; i += blockDim.x)
-            buf[i] = (i < d) ? val[b + i] : INT32_MAX;
-        __syncthreads();
-        for (int32_t k = 2; k <= n2; k <<= 1) {
-            for (int32_t j = k >> 1; j > 0; j >>= 1) {
-                for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-                    int32_t l = i ^ j;
-                    if (l > i) {
-                        int32_t x = buf[i], y = buf[l];
-                        bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            buf[i] = y;
-                            buf[l] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (int32_t i = threadIdx.x; i < d; i += blockDim.x) val[b + i] = buf[i];
-        __syncthreads();
-    }
-}
-
-__global__ void k_big_load(const int32_t *src, int32_t len, int32_t n2, int32_t *tmp) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
-         i += (int64_t)gridDim.x * blockDim.x)
-        tmp[i] = (i < len) ? src[i] : INT32_MAX;
-}
-
-__global__ void k_bitonic_step(int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t l = i ^ j;
-        if (l > i) {
-            int32_t x = tmp[i], y = tmp[l];
-            bool up = (i & k) == 0;
-            if ((x > y) == up) {
-                tmp[i] = y;
-                tmp[l] = x;
-            }
-        }
+// Row pointers of the transpose from the sorted members: ptr[v] = first slot
+// with member >= v, for v = 0..n (members outside [0, n) are clamped; they
+// only occur in input that the row checks reject).
+__global__ void k_rs_bounds(const int32_t *sk, int64_t nnz, int32_t n, int32_t *ptr) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nnz;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int32_t hi = p < nnz ? sk[p] : n;
+        int32_t lo = p > 0 ? sk[p - 1] : -1;
+        hi = hi < 0 ? 0 : (hi > n ? n : hi);
+        lo = lo < -1 ? -1 : (lo > n ? n : lo);
+        for (int32_t v = lo + 1; v <= hi; ++v) ptr[v] = (int32_t)p;
     }
 }
 
@@ -361,27 +377,75 @@ __global__ void k_filter_scatter(const int32_t *itmM, int64_t nnz, const int32_t
     }
 }
 
-// One wave per item (grid-stride): W_a = sum over members v of the number of
-// kept items b > a in N_s(v); 0 for items with |S_a| < s.  For every member
-// incidence k of a kept item, start[k] = index in itmS of the first item > a
-// in N_s(v) (the back-pointer where a's walk over v begins).
+// Short rows are walked by groups of kGroup lanes (eight rows per wave);
+// longer rows by whole waves, in a second launch that looks at 64 rows at a
+// time and takes the long ones in turn.  Short means at most 32 entries.
+constexpr int kGroup = 8;
+
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int d = W / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ uint64_t group_max(uint64_t v) {
+#pragma unroll
+    for (int d = W / 2; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Call body(a, gl) for the rows a this launch owns: with W < kWave, every
+// row of at most SHORT entries, by a group of W lanes (gl = lane in the
+// group); with W == kWave, every longer row, by the whole wave.
+template <int W, int SHORT, typename Body>
+__device__ __forceinline__ void for_rows(const int32_t *ptrI, int64_t N, Body body) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    if (W < kWave) {
+        constexpr int G = kWave / W;
+        const int gl = lane & (W - 1);
+        for (int64_t a = wave * G + lane / W; a < N; a += nwaves * G) {
+            if (ptrI[a + 1] - ptrI[a] > SHORT) continue;  // the whole-wave launch takes it
+            body(a, gl);
+        }
+    } else {
+        for (int64_t base = wave * kWave; base < N; base += nwaves * kWave) {
+            const int64_t r = base + lane;
+            uint64_t m = __ballot(r < N && ptrI[r + 1] - ptrI[r] > SHORT);
+            while (m) {
+                const int64_t a = base + __builtin_ctzll(m);
+                m &= m - 1;
+                body(a, lane);
+            }
+        }
+    }
+}
+
+// W_a = sum over members v of the number of kept items b > a in N_s(v); 0 for
+// items with |S_a| < s.  For every member incidence k of a kept item,
+// start[k] = index in itmS of the first item > a in N_s(v) (the back-pointer
+// where a's walk over v begins).  totals: kept items, their incidences, W.
+template <int W>
 __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t *memI,
                                               int32_t N, int32_t s, const int32_t *s_item,
                                               const int32_t *ptrS, const int32_t *itmS,
                                               int64_t *cost, int32_t *start, int64_t *totals,
                                               int32_t full, int32_t have_start) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    int64_t kept = 0, kept_nnz = 0, wedges = 0;
-    for (int64_t a = wave; a < N; a += nwaves) {
+    int64_t kept = 0, kept_nnz = 0, wedges = 0;  // counted by each row's first lane
+    for_rows<W, 32>(ptrI, N, [&](int64_t a, int gl) {
         const int32_t b = ptrI[a], e = ptrI[a + 1];
         if (e - b < (s_item ? s_item[a] : s)) {
-            if (lane == 0) cost[a] = 0;
-            continue;
+            if (gl == 0) cost[a] = 0;
+            return;
         }
         int64_t c = 0;
-        for (int32_t k = b + lane; k < e; k += kWave) {
+        for (int32_t k = b + gl; k < e; k += W) {
             const int32_t v = memI[k];
             const int32_t lo = ptrS[v], hi = ptrS[v + 1];
             int32_t st;
@@ -393,16 +457,21 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
             }
             c += hi - st;
         }
-        c = wave_sum(c);
-        if (lane == 0) cost[a] = c;
-        kept += 1;
-        kept_nnz += e - b;
-        wedges += c;
-    }
+        c = group_sum<W>(c);
+        if (gl == 0) {
+            cost[a] = c;
+            kept += 1;
+            kept_nnz += e - b;
+            wedges += c;
+        }
+    });
     // one atomic per counter and block (same-address atomics serialize)
+    kept = wave_sum(kept);
+    kept_nnz = wave_sum(kept_nnz);
+    wedges = wave_sum(wedges);
     __shared__ int64_t red[3][256 / kWave];
     const int wid = threadIdx.x / kWave;
-    if (lane == 0) {
+    if (lane_id() == 0) {
         red[0][wid] = kept;
         red[1][wid] = kept_nnz;
         red[2][wid] = wedges;
@@ -415,50 +484,78 @@ __global__ __launch_bounds__(256) void k_cost(const int32_t *ptrI, const int32_t
     }
 }
 
-// One wave per kept item: flag as lookup-only the min(s - 1, kMaxLookup)
-// members with the most candidates after a (ties to the lower incidence), by
-// setting the sign bit of start[k].  At least one member stays unflagged, as
-// |S_a| >= s for a kept item.  The item's planning cost becomes the wedges of
-// its inserting members (they fill the table), but at least a third of W_a
-// (every wedge is still read).
+// Per kept item: flag as lookup-only the min(s - 1, kMaxLookup) members with
+// the most candidates after a (ties to the lower incidence), by setting the
+// sign bit of start[k].  At least one member stays unflagged, as |S_a| >= s
+// for a kept item.  The item's planning cost becomes the wedges of its
+// inserting members (they fill the table), but at least a third of W_a
+// (every wedge is still read).  A row of at most W * kKeysPerLane members
+// keeps its keys in registers, so the rounds only exchange maxima; longer
+// rows read their members again in every round.  The lane that owns
+// incidence k is the one that flags it.
+constexpr int kKeysPerLane = 4;
+
+template <int W>
 __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const int32_t *memI,
                                                      int32_t N, int32_t s_all,
                                                      const int32_t *s_item, const int32_t *ptrS,
                                                      int32_t *start, int64_t *cost) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t a = wave; a < N; a += nwaves) {
+    for_rows<W, kGroup * kKeysPerLane>(ptrI, N, [&](int64_t a, int gl) {
         const int32_t b = ptrI[a], e = ptrI[a + 1];
         const int32_t s = s_item ? s_item[a] : s_all;
-        if (e - b < s) continue;
+        if (e - b < s) return;
         const int32_t rounds = min(min(s - 1, kMaxLookup), e - b - 1);
         int64_t flagged = 0;
-        for (int32_t r = 0; r < rounds; ++r) {
+        if (e - b <= W * kKeysPerLane) {
+            uint64_t key[kKeysPerLane];
+#pragma unroll
+            for (int i = 0; i < kKeysPerLane; ++i) {
+                const int32_t k = b + gl + i * W;
+                key[i] = 0;
+                if (k < e) {
+                    const int32_t st = start[k];
+                    const int32_t c = ptrS[memI[k] + 1] - st;
+                    if (st >= 0)
+                        key[i] = ((uint64_t)(uint32_t)c << 32) | (uint32_t)(INT32_MAX - k);
+                }
+            }
+            for (int32_t r = 0; r < rounds; ++r) {
+                uint64_t best = 0;
+#pragma unroll
+                for (int i = 0; i < kKeysPerLane; ++i) best = key[i] > best ? key[i] : best;
+                best = group_max<W>(best);
+                if ((best >> 32) == 0) break;  // no member with candidates left
+                const int32_t k = INT32_MAX - (int32_t)(uint32_t)best;
+#pragma unroll
+                for (int i = 0; i < kKeysPerLane; ++i) {
+                    if (key[i] == best) {  // keys are distinct: one owner
+                        key[i] = 0;
+                        start[k] |= (int32_t)0x80000000u;
+                    }
+                }
+                flagged += (int64_t)(best >> 32);
+            }
+        } else for (int32_t r = 0; r < rounds; ++r) {
             // best unflagged member: most candidates, then lowest k
             uint64_t best = 0;
-            for (int32_t k = b + lane; k < e; k += kWave) {
+            for (int32_t k = b + gl; k < e; k += W) {
                 const int32_t st = start[k];
                 if (st < 0) continue;
                 const int32_t c = ptrS[memI[k] + 1] - st;
                 const uint64_t key = ((uint64_t)(uint32_t)c << 32) | (uint32_t)(INT32_MAX - k);
                 best = key > best ? key : best;
             }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint64_t o = __shfl_xor(best, d, kWave);
-                best = o > best ? o : best;
-            }
+            best = group_max<W>(best);
             if ((best >> 32) == 0) break;  // no member with candidates left
             const int32_t k = INT32_MAX - (int32_t)(uint32_t)best;
-            if (lane == 0) start[k] |= (int32_t)0x80000000u;
+            if ((k - b) % W == gl) start[k] |= (int32_t)0x80000000u;
             flagged += (int64_t)(best >> 32);
         }
-        if (lane == 0 && flagged) {
+        if (gl == 0 && flagged) {
             const int64_t w = cost[a];
             cost[a] = max(w - flagged, (w + 2) / 3);
         }
-    }
+    });
 }
 
 // Product filter, one block per tile of kFilterTile entries (256 threads x
@@ -524,12 +621,6 @@ hipError_t launch_rows(hipStream_t st, const int32_t *rp, const int32_t *col, in
     return hipGetLastError();
 }
 
-hipError_t launch_degree(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
-                         int32_t *deg) {
-    if (nnz <= 0) return hipSuccess;
-    k_degree<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(col, nnz, n, deg);
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v) {
     if (n <= 0) return hipSuccess;
@@ -574,19 +665,7 @@ hipError_t launch_scan_i32_to_i64(hipStream_t st, const int32_t *in, int64_t n, 
     return scan_impl<int32_t, int64_t>(st, in, n, out, partial);
 }
 
-hipError_t launch_scatter(hipStream_t st, const int32_t *col, const int32_t *rowid, int64_t nnz,
-                          int32_t n, const int32_t *ptrT, int32_t *fill, int32_t *colT) {
-    if (nnz <= 0) return hipSuccess;
-    k_scatter<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(col, rowid, nnz, n, ptrT, fill, colT);
-    return hipGetLastError();
-}
 
-hipError_t launch_transpose_fix(hipStream_t st, int64_t nnz, const int32_t *rowid, int32_t *colT,
-                                int32_t *kT, int32_t *posT) {
-    if (nnz <= 0) return hipSuccess;
-    k_transpose_fix<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(nnz, rowid, colT, kT, posT);
-    return hipGetLastError();
-}
 
 hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map, int32_t *start) {
     if (nnz <= 0) return hipSuccess;
@@ -594,41 +673,41 @@ hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map
     return hipGetLastError();
 }
 
-hipError_t launch_segsort_classify(hipStream_t st, const int32_t *ptr, int32_t n,
-                                   int32_t *mid_list, int32_t *big_list, int32_t *counts) {
-    if (n <= 0) return hipSuccess;
-    k_segsort_classify<<<grid_for(n, 256, 65536), 256, 0, st>>>(ptr, n, mid_list, big_list,
-                                                                 counts);
-    return hipGetLastError();
-}
 
-hipError_t launch_segsort_small(hipStream_t st, const int32_t *ptr, int32_t n, int32_t *val) {
-    if (n <= 0) return hipSuccess;
-    k_segsort_small<<<grid_for(n, 256, 65536), 256, 0, st>>>(ptr, n, val);
-    return hipGetLastError();
-}
 
-hipError_t launch_segsort_mid(hipStream_t st, const int32_t *ptr, const int32_t *mid_list,
-                              const int32_t *counts, int32_t grid, int32_t *val) {
-    if (grid <= 0) return hipSuccess;
-    k_segsort_mid<<<grid, 256, 0, st>>>(ptr, mid_list, counts, val);
-    return hipGetLastError();
-}
 
-hipError_t launch_segsort_big_load(hipStream_t st, const int32_t *src, int32_t len, int32_t n2,
-                                   int32_t *tmp) {
-    k_big_load<<<grid_for(n2, 256, 65536), 256, 0, st>>>(src, len, n2, tmp);
-    return hipGetLastError();
-}
 
-hipError_t launch_bitonic_step(hipStream_t st, int32_t *tmp, int32_t n2, int32_t k, int32_t j) {
-    k_bitonic_step<<<grid_for(n2, 256, 65536), 256, 0, st>>>(tmp, n2, k, j);
-    return hipGetLastError();
-}
 
-hipError_t launch_segsort_big_store(hipStream_t st, const int32_t *tmp, int32_t len,
-                                    int32_t *dst) {
-    k_copy<<<grid_for(len, 256, 65536), 256, 0, st>>>(dst, tmp, len);
+
+int64_t transpose_tiles(int64_t nnz) { return (nnz + kRsTile - 1) / kRsTile; }
+
+hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
+                            const int32_t *rowid, int32_t *const rsK[2], int32_t *const rsV[2],
+                            int32_t *hist, int32_t *part32, int32_t *ptrT, int32_t *colT,
+                            int32_t *kT, int32_t *posT) {
+    if (nnz <= 0) return launch_fill_i32(st, ptrT, (int64_t)n + 1, 0);
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+    const int passes = std::max(1, (bits + kRsBits - 1) / kRsBits);
+    const int32_t ntiles = (int32_t)transpose_tiles(nnz);
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < passes && e == hipSuccess; ++p) {
+        const int32_t *kin = p == 0 ? col : rsK[(p - 1) & 1];
+        const int32_t *vin = p == 0 ? nullptr : rsV[(p - 1) & 1];
+        const int last = p == passes - 1;
+        k_rs_hist<<<ntiles, kRsThreads, 0, st>>>(kin, nnz, p * kRsBits, hist, ntiles);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_scan_i32(st, hist, (int64_t)kRsBins * ntiles, hist, part32);
+        if (e == hipSuccess) {
+            k_rs_scatter<<<ntiles, kRsThreads, 0, st>>>(kin, vin, nnz, p * kRsBits, hist, ntiles,
+                                                       rsK[p & 1], rsV[p & 1], last, rowid, colT,
+                                                       kT, posT);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return e;
+    k_rs_bounds<<<grid_for(nnz + 1, 256, 65536), 256, 0, st>>>(rsK[(passes - 1) & 1], nnz, n,
+                                                               ptrT);
     return hipGetLastError();
 }
 
@@ -655,7 +734,11 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
                        int64_t *cost, int32_t *start, int64_t *totals, int32_t full,
                        int32_t have_start) {
     if (N <= 0) return hipSuccess;
-    k_cost<<<grid_for((int64_t)N * kWave, 256, 4096), 256, 0, st>>>(
+    k_cost<kGroup><<<grid_for((int64_t)N * kGroup, 256, 4096), 256, 0, st>>>(
+        ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals, full, have_start);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cost<kWave><<<grid_for(N, 256, 1024), 256, 0, st>>>(
         ptrI, memI, N, s, s_item, ptrS, itmS, cost, start, totals, full, have_start);
     return hipGetLastError();
 }
@@ -664,7 +747,11 @@ hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t
                               int32_t s, const int32_t *s_item, int32_t s_max,
                               const int32_t *ptrS, int32_t *start, int64_t *cost) {
     if (N <= 0 || s_max <= 1) return hipSuccess;
-    k_mark_lookup<<<grid_for((int64_t)N * kWave, 256, 65536), 256, 0, st>>>(
+    k_mark_lookup<kGroup><<<grid_for((int64_t)N * kGroup, 256, 65536), 256, 0, st>>>(
+        ptrI, memI, N, s, s_item, ptrS, start, cost);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_mark_lookup<kWave><<<grid_for(N, 256, 4096), 256, 0, st>>>(
         ptrI, memI, N, s, s_item, ptrS, start, cost);
     return hipGetLastError();
 }
