@@ -257,7 +257,7 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
 
 // Task arrays, sized once the task count is known.
 struct TaskLayout {
-    int32_t *item, *part, *small, *big, *cnt, *need, *ctrs;
+    int32_t *item, *part, *small, *small_item, *big, *cnt, *need, *ctrs;
     int64_t *off, *part64;
     unsigned long long *pool_head;
     StageRec *log;
@@ -274,6 +274,7 @@ TaskLayout plan_tasks(Arena &A, int64_t T) {
     L.item = A.take<int32_t>(T);
     L.part = A.take<int32_t>(T);
     L.small = A.take<int32_t>(T);
+    L.small_item = A.take<int32_t>(T);
     L.big = A.take<int32_t>(T);
     L.cnt = A.take<int32_t>(T);
     L.off = A.take<int64_t>(T + 1);
@@ -646,7 +647,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     TA.base = reinterpret_cast<char *>(c->ws2);
     const TaskLayout TL = plan_tasks(TA, T);
     hip_check(c, launch_task_fill(st, L.cost, (int32_t)N, tu, L.tbase, TL.item, TL.part, TL.small,
-                                  TL.big, L.tcounts),
+                                  TL.small_item, TL.big, L.tcounts),
               "task fill");
     mark(c, 2);
     // 7. one counting pass: pairs per task, each range's pairs staged in a pool
@@ -680,6 +681,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.task_part = TL.part;
     C.n_tasks = (int32_t)T;
     C.small_tasks = TL.small;
+    C.small_items = TL.small_item;
     C.big_tasks = TL.big;
     C.task_counts = L.tcounts;
     C.queue = L.queue;

@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
     for (int32_t r = blockIdx.x; r < n_small; r += gridDim.x) {
         const int32_t t = A.small_tasks[r];
         if (A.mode == kModeFill && A.need && !A.need[t]) continue;
-        const int32_t a = A.task_item[t];
+        const int32_t a = A.small_items[r];
         const int64_t c = A.cost[a];
         // 2 W_a home slots (load <= 1/2), rounded up to whole waves
         int32_t want = (int32_t)std::min<int64_t>(2 * c, kSmallSlots);
@@ -895,8 +895,7 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         init_cursors<kWave>(A, a, A.full ? 0 : a + 1, k0, k1, cur, end, lookm);
         const int64_t produced = run_range<kWave, kSmallPad, kSmallRunCap>(
             A, S, a, A.s_item ? A.s_item[a] : A.s, nend, t, A.full ? 0 : a + 1, nend, want,
-            count_bits(k1 - k0),
-            k0, k1, cur, end, lookm, passes);
+            count_bits(k1 - k0), k0, k1, cur, end, lookm, passes);
         if (A.mode != kModeFill && threadIdx.x == 0) A.task_cnt[t] = (int32_t)produced;
         __syncthreads();
     }
@@ -1013,8 +1012,9 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
                                                    int32_t small_max, int32_t target,
                                                    int32_t group, const int64_t *tbase,
                                                    int32_t *task_item, int32_t *task_part,
-                                                   int32_t *small_tasks, int32_t *groups,
-                                                   int32_t *counts, int32_t chunk) {
+                                                   int32_t *small_tasks, int32_t *small_items,
+                                                   int32_t *groups, int32_t *counts,
+                                                   int32_t chunk) {
     __shared__ int32_t sh[2];
     const int lane = lane_id();
     const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -1063,7 +1063,11 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
         int32_t sbase = 0;
         if (lane == 0 && sm) sbase = atomicAdd(&sh[0], (int32_t)__popcll(sm));
         sbase = __shfl(sbase, 0, kWave);
-        if (small) small_tasks[sbase + (int32_t)lanes_below(sm)] = (int32_t)t0;
+        if (small) {
+            const int32_t q = sbase + (int32_t)lanes_below(sm);
+            small_tasks[q] = (int32_t)t0;
+            small_items[q] = (int32_t)a;
+        }
         int32_t incl = G;  // inclusive prefix of G over the wave
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
@@ -1146,14 +1150,16 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
 
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
-                            int32_t *small_tasks, int32_t *big_tasks, int32_t *counts) {
+                            int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
+                            int32_t *counts) {
     if (N <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
     const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
     const int64_t grid = ((int64_t)N + chunk - 1) / chunk;
     k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges,
                                                 std::max(1, tu.group_parts), tbase, task_item,
-                                                task_part, small_tasks, big_tasks, counts, chunk);
+                                                task_part, small_tasks, small_items, big_tasks,
+                                                counts, chunk);
     return hipGetLastError();
 }
 

@@ -121,7 +121,8 @@ hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t
 
 // Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
 // candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is
-// listed in small_tasks (W_a <= small_max) or big_tasks; counts[0] / [1]
+// listed in small_tasks, with its item in small_items (W_a <= small_max), or
+// in big_tasks; counts[0] / [1]
 // receive the list lengths.
 hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                              int32_t *ntask);
@@ -129,7 +130,8 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
 // item, the index of the group's first task; counts[1] = number of groups.
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
-                            int32_t *small_tasks, int32_t *big_tasks, int32_t *counts);
+                            int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
+                            int32_t *counts);
 
 // Counting-kernel modes.
 enum : int32_t {
@@ -158,6 +160,7 @@ struct CountArgs {
     const int32_t *task_item, *task_part;
     int32_t n_tasks;
     const int32_t *small_tasks, *big_tasks;
+    const int32_t *small_items;  // item of each small task
     const int32_t *task_counts;  // [0] small tasks, [1] task groups
     int32_t *queue;              // big-task queue head (reset by the launcher)
     int32_t *task_cnt;           // count mode: pairs per task

@@ -83,6 +83,56 @@ inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
 
 // ------------------------------------------------------------- checks
 
+// Short rows are walked by groups of kGroup lanes (eight rows per wave);
+// longer rows by whole waves, in a second launch that looks at 64 rows at a
+// time and takes the long ones in turn.  Short means at most 32 entries.
+constexpr int kGroup = 8;
+
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int d = W / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ uint64_t group_max(uint64_t v) {
+#pragma unroll
+    for (int d = W / 2; d >= 1; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Call body(a, gl) for the rows a this launch owns: with W < kWave, every
+// row of at most SHORT entries, by a group of W lanes (gl = lane in the
+// group); with W == kWave, every longer row, by the whole wave.
+template <int W, int SHORT, typename Body>
+__device__ __forceinline__ void for_rows(const int32_t *ptrI, int64_t N, Body body) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    if (W < kWave) {
+        constexpr int G = kWave / W;
+        const int gl = lane & (W - 1);
+        for (int64_t a = wave * G + lane / W; a < N; a += nwaves * G) {
+            if (ptrI[a + 1] - ptrI[a] > SHORT) continue;  // the whole-wave launch takes it
+            body(a, gl);
+        }
+    } else {
+        for (int64_t base = wave * kWave; base < N; base += nwaves * kWave) {
+            const int64_t r = base + lane;
+            uint64_t m = __ballot(r < N && ptrI[r + 1] - ptrI[r] > SHORT);
+            while (m) {
+                const int64_t a = base + __builtin_ctzll(m);
+                m &= m - 1;
+                body(a, lane);
+            }
+        }
+    }
+}
+
 __global__ void k_check_rowptr(const int32_t *rp, int32_t m, int32_t *err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && rp[0] != 0) atomicOr(err, kErrRowPtr0);
@@ -91,24 +141,22 @@ __global__ void k_check_rowptr(const int32_t *rp, int32_t m, int32_t *err) {
 
 // One wave per row (grid-stride): the row id of every incidence, member range
 // checks and, when asked, the strictly-increasing check of each row.
+template <int W>
 __global__ __launch_bounds__(256) void k_rows(const int32_t *rp, const int32_t *col, int32_t m,
                                               int32_t n, int64_t nnz, int check_order,
                                               int32_t *rowid, int32_t *err) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     int32_t bad = 0;
-    for (int64_t i = wave; i < m; i += nwaves) {
+    for_rows<W, 32>(rp, m, [&](int64_t i, int gl) {
         int64_t b = rp[i], e = rp[i + 1];
         if (b < 0) b = 0;
         if (e > nnz) e = nnz;
-        for (int64_t k = b + lane; k < e; k += kWave) {
+        for (int64_t k = b + gl; k < e; k += W) {
             int32_t v = col[k];
             rowid[k] = (int32_t)i;
             if (v < 0 || v >= n) bad |= kErrColRange;
             if (check_order && k + 1 < e && col[k + 1] <= v) bad |= kErrColOrder;
         }
-    }
+    });
     if (bad) atomicOr(err, bad);
 }
 
@@ -377,56 +425,6 @@ __global__ void k_filter_scatter(const int32_t *itmM, int64_t nnz, const int32_t
     }
 }
 
-// Short rows are walked by groups of kGroup lanes (eight rows per wave);
-// longer rows by whole waves, in a second launch that looks at 64 rows at a
-// time and takes the long ones in turn.  Short means at most 32 entries.
-constexpr int kGroup = 8;
-
-template <int W, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int d = W / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-template <int W>
-__device__ __forceinline__ uint64_t group_max(uint64_t v) {
-#pragma unroll
-    for (int d = W / 2; d >= 1; d >>= 1) {
-        const uint64_t o = __shfl_xor(v, d, kWave);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
-// Call body(a, gl) for the rows a this launch owns: with W < kWave, every
-// row of at most SHORT entries, by a group of W lanes (gl = lane in the
-// group); with W == kWave, every longer row, by the whole wave.
-template <int W, int SHORT, typename Body>
-__device__ __forceinline__ void for_rows(const int32_t *ptrI, int64_t N, Body body) {
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    if (W < kWave) {
-        constexpr int G = kWave / W;
-        const int gl = lane & (W - 1);
-        for (int64_t a = wave * G + lane / W; a < N; a += nwaves * G) {
-            if (ptrI[a + 1] - ptrI[a] > SHORT) continue;  // the whole-wave launch takes it
-            body(a, gl);
-        }
-    } else {
-        for (int64_t base = wave * kWave; base < N; base += nwaves * kWave) {
-            const int64_t r = base + lane;
-            uint64_t m = __ballot(r < N && ptrI[r + 1] - ptrI[r] > SHORT);
-            while (m) {
-                const int64_t a = base + __builtin_ctzll(m);
-                m &= m - 1;
-                body(a, lane);
-            }
-        }
-    }
-}
-
 // W_a = sum over members v of the number of kept items b > a in N_s(v); 0 for
 // items with |S_a| < s.  For every member incidence k of a kept item,
 // start[k] = index in itmS of the first item > a in N_s(v) (the back-pointer
@@ -616,8 +614,12 @@ hipError_t launch_check_rowptr(hipStream_t st, const int32_t *rp, int32_t m, int
 hipError_t launch_rows(hipStream_t st, const int32_t *rp, const int32_t *col, int32_t m,
                        int32_t n, int64_t nnz, int check_order, int32_t *rowid, int32_t *err) {
     if (m <= 0) return hipSuccess;
-    k_rows<<<grid_for((int64_t)m * kWave, 256, 65536), 256, 0, st>>>(rp, col, m, n, nnz,
-                                                                    check_order, rowid, err);
+    k_rows<kGroup><<<grid_for((int64_t)m * kGroup, 256, 65536), 256, 0, st>>>(
+        rp, col, m, n, nnz, check_order, rowid, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_rows<kWave><<<grid_for(m, 256, 4096), 256, 0, st>>>(rp, col, m, n, nnz, check_order, rowid,
+                                                         err);
     return hipGetLastError();
 }
 
