@@ -532,6 +532,12 @@ __device__ __forceinline__ uint32_t slot_count(uint32_t w, const Range &R) {
     return R.mul ? (w & R.cmask) : w;
 }
 
+__device__ __forceinline__ void cswap(uint32_t &x, uint32_t &y) {
+    const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+    x = lo;
+    y = hi;
+}
+
 __device__ __forceinline__ bool bucket_full(const uint4 &q) {
     return q.x != 0u && q.y != 0u && q.z != 0u && q.w != 0u;
 }
@@ -674,17 +680,23 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                     }
                 }
             } else {
-                uint32_t tag[4];
+                // the bucket's kept words in candidate order (a word orders
+                // like its key, which sits above the count bits; words not
+                // kept sort last): five compare-exchanges
+                uint32_t key[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) tag[k] = wv[k] >> R.cb;
-                // rank inside the bucket by candidate
+                for (int k = 0; k < 4; ++k) key[k] = ok[k] ? wv[k] : 0xFFFFFFFFu;
+                cswap(key[0], key[1]);
+                cswap(key[2], key[3]);
+                cswap(key[0], key[2]);
+                cswap(key[1], key[3]);
+                cswap(key[1], key[2]);
+                uint32_t tag[4];
                 int32_t rank[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    rank[k] = 0;
-#pragma unroll
-                    for (int k2 = 0; k2 < 4; ++k2)
-                        if (k2 != k) rank[k] += ok[k2] && tag[k2] < tag[k];
+                    tag[k] = key[k] >> R.cb;
+                    rank[k] = k;
                 }
                 // runs of full buckets: a bucket ends a run unless it is full
                 const bool full = bucket_full(q) && bk < b1;
@@ -726,11 +738,11 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                 const int32_t pos = run + before - left;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (ok[k]) {
+                    if (k < n) {
                         const int32_t p = pos + rank[k];
                         if (dst_a) dst_a[base + p] = a - shift;
                         dst_b[base + p] = R.lo + (int32_t)tag[k] - 1 - shift;
-                        if (dst_w) dst_w[base + p] = (int32_t)c[k];
+                        if (dst_w) dst_w[base + p] = (int32_t)(key[k] & R.cmask);
                     }
                 }
                 prev_full = ((fm >> 63) & 1ull) != 0;
