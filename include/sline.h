@@ -232,10 +232,15 @@ typedef struct {
 
 /* Start a server on `device` with `n_workers` (1..16) worker threads.
  * hbm_budget_bytes caps the estimated device memory of the batches running
- * at once (a single query above the cap still runs, alone); max_batch caps the
- * queries per batch.  The estimate of a query is about 80 bytes per incidence
- * plus 20 bytes per pair the result can hold (W_1 / s, where W_1 is the sum
- * over members of C(degree, 2) on the query's side, at most N(N - 1) / 2). */
+ * at once plus the results handed over and not yet released (a single query
+ * above the cap still runs, alone, when nothing else runs); max_batch caps
+ * the queries per batch.  The estimate of a query is about 80 bytes per
+ * incidence plus 20 bytes per pair the result can hold (W_1 / s, where W_1 is
+ * the sum over members of C(degree, 2) on the query's side, at most
+ * N(N - 1) / 2).  The server reserves the budget as device memory when it
+ * starts (if the device has it to spare) and holds its memory until
+ * sline_server_destroy; beyond the reservation it grows only while a
+ * sixteenth of the device (at least 16 GiB) stays free. */
 sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_budget_bytes,
                                  int32_t max_batch, int32_t n_workers);
 

@@ -51,11 +51,13 @@ struct Graph {
 // Device memory of the workers (and of handed-over results): large chunks
 // from hipMalloc, carved into blocks by best fit and merged again on release,
 // so the serving loop maps device memory once instead of per query (mapping
-// fresh memory costs more than most builds).  A chunk is only requested when
-// the device reports the memory free: a hipMalloc that fails for lack of
-// memory can take seconds, during which no worker could allocate.  (The
-// budget itself is kept by admission, which lets a query larger than the
-// budget run alone.)  When no chunk has room,
+// fresh memory costs more than most builds).  The budget is reserved as one
+// chunk when the server starts.  A further chunk is only requested while the
+// device keeps a sixteenth of its memory (at least 16 GiB) free: near a full
+// device, hipMalloc calls were measured at seconds each, failing or not,
+// and no worker could allocate meanwhile.  (The budget itself is kept by
+// admission, which lets a query larger than the budget run alone.)  When no
+// chunk has room,
 // chunks with nothing allocated are returned first; if that does not make
 // room the request fails at once and the library takes its fallback (a
 // smaller staging pool, or an error the worker answers by running the
@@ -71,7 +73,6 @@ struct DeviceCache {
     std::map<void *, std::pair<Chunk *, size_t>> live;  // block -> (chunk, length)
     size_t chunk_min = (size_t)4 << 30;
     size_t total = 0;                           // bytes the chunks add up to
-    static constexpr size_t kHeadroom = (size_t)1 << 30;  // left free on the device
     // device calls made so far (reported by the server log)
     int64_t n_malloc = 0, n_malloc_fail = 0, n_free = 0, ns_malloc = 0, ns_free = 0;
 
@@ -100,17 +101,40 @@ struct DeviceCache {
         return p;
     }
 
-    // bytes a new chunk for a request of n bytes may have (0: the device
-    // has not that much free)
-    size_t grow_size(size_t n) const {
+    // device memory a new chunk may take: what is free beyond the headroom
+    static size_t growable() {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             (void)hipGetLastError();
             return 0;
         }
-        const size_t avail = fr > kHeadroom ? fr - kHeadroom : 0;
+        const size_t headroom = std::max((size_t)16 << 30, tot / 16);
+        return fr > headroom ? fr - headroom : 0;
+    }
+
+    // bytes a new chunk for a request of n bytes may have (0: none)
+    size_t grow_size(size_t n) const {
+        const size_t avail = growable();
         if (n > avail) return 0;
         return std::min(std::max(n, chunk_min), avail);
+    }
+
+    // one chunk of up to `bytes` (less if the device has less to spare)
+    void reserve(size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        const size_t sz = round(std::min(bytes, growable()));
+        if (sz < chunk_min) return;
+        void *base = nullptr;
+        if (hipMalloc(&base, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        Chunk *c = new Chunk();
+        c->base = static_cast<char *>(base);
+        c->size = sz;
+        c->free[0] = sz;
+        chunks.push_back(c);
+        total += sz;
     }
 
     void *alloc(size_t n) {
@@ -236,6 +260,7 @@ struct sline_server {
     std::unordered_map<int64_t, Query> queries;   // every ticket not yet handed over
     int64_t next_ticket = 1;
     int64_t in_flight = 0;                        // estimated bytes of running batches
+    int64_t held = 0;                             // bytes of results not yet released
     int32_t running = 0;                          // batches on the device
     bool stop = false;
     struct Worker {
@@ -251,6 +276,11 @@ struct sline_server {
 
 namespace {
 
+// Device bytes a handed-over result holds until it is released.
+int64_t result_bytes(const sline_edges &e) {
+    return (int64_t)sizeof(int32_t) * e.n_pairs * (e.w ? 3 : 2);
+}
+
 int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual) {
     const double N = dual ? g.H.n_vertices : g.H.n_edges;
     const double pairs = std::min(g.w1[dual] / std::max(s, 1), N * (N - 1.0) / 2.0);
@@ -259,7 +289,7 @@ int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual)
 
 void worker_loop(sline_server *S, int wi) {
     sline_server::Worker &W = S->workers[wi];
-    hipSetDevice(S->device);
+    (void)hipSetDevice(S->device);
     for (;;) {
         std::vector<int64_t> batch;
         int64_t est = 0;
@@ -271,8 +301,10 @@ void worker_loop(sline_server *S, int wi) {
                 // a query larger than the budget runs alone when nothing else does
                 while (!S->queue.empty() && (int32_t)batch.size() < S->max_batch) {
                     Query &q = S->queries[S->queue.front()];
+                    // results the client has not released count against the
+                    // budget too (so a slow client holds back admission)
                     const bool alone = S->in_flight == 0 && batch.empty();
-                    if (!alone && S->in_flight + est + q.est > S->budget) break;
+                    if (!alone && S->in_flight + S->held + est + q.est > S->budget) break;
                     est += q.est;
                     batch.push_back(q.ticket);
                     S->queue.pop_front();
@@ -367,6 +399,7 @@ void worker_loop(sline_server *S, int wi) {
                 if (qst[g] == SLINE_OK) {
                     q.out = outs[g];
                     q.info.n_pairs = outs[g].n_pairs;
+                    S->held += result_bytes(outs[g]);
                 }
                 q.done = true;
             }
@@ -409,6 +442,7 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
     al.free = cache_free;
     al.user = &S->cache;
     S->log = getenv("SLINE_SERVER_LOG") != nullptr;
+    S->cache.reserve((size_t)hbm_budget_bytes);
     S->workers.resize(n_workers);
     for (auto &W : S->workers) {
         if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
@@ -512,7 +546,12 @@ sline_status sline_server_poll(sline_server *S, int64_t ticket, sline_edges *out
 
 sline_status sline_server_release(sline_server *S, sline_edges *out) {
     if (!S || !out) return SLINE_EINVAL;
+    if (out->a || out->b) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->held = std::max<int64_t>(0, S->held - result_bytes(*out));
+    }
     free_arrays(S, *out);
+    S->cv.notify_all();  // admission may have waited on the released memory
     out->a = out->b = out->w = nullptr;
     out->n_pairs = 0;
     return SLINE_OK;
