@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--catalog-small", type=int, default=256)
     p.add_argument("--catalog-large", type=int, default=2)
     p.add_argument("--budget-gb", type=float, default=160.0)
-    p.add_argument("--workers", type=int, default=2)
+    p.add_argument("--workers", type=int, default=3)
     p.add_argument("--graphs", type=int, default=512, help="batch form: number of graphs")
     p.add_argument("--spgemm", action="store_true",
                    help="plain/dual forms: take the product route (sline_build_spgemm)")
