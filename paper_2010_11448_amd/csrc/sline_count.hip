@@ -189,8 +189,11 @@ __device__ __forceinline__ uint32_t pick4(int32_t i, uint32_t a0, uint32_t a1, u
 // bucket was full when it came, in a later one, and a bucket with a free word
 // ends any search.  Wedges whose home bucket is full, or whose free word was
 // taken by another key meanwhile, finish in the probe loop.
-__device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t j0, int32_t j1,
-                                         int32_t j2, int32_t j3) {
+__device__ __forceinline__ bool tab_add4(uint32_t *tab, uint32_t *spare, const Range &R,
+                                         int32_t j0, int32_t j1, int32_t j2, int32_t j3) {
+    // this lane's spare word: atomics with nothing to count go there, so the
+    // atomics need no branches
+    uint32_t *const dummy = spare + lane_id();
     const int32_t j[4] = {j0, j1, j2, j3};
     uint32_t x[4];
     bool in[4];
@@ -201,8 +204,7 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
     }
     if (R.mul == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (in[i]) atomicAdd(&tab[x[i]], 1u);
+        for (int i = 0; i < 4; ++i) atomicAdd(in[i] ? &tab[x[i]] : dummy, 1u);
         return true;
     }
     const uint32_t hmask = ~R.cmask;
@@ -235,28 +237,22 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, const Range &R, int32_t 
         if ((w1 ^ tag[i]) <= R.cmask) hit = 1;
         if ((w0 ^ tag[i]) <= R.cmask) hit = 0;
         addr[i] = 4u * (uint32_t)b[i] + (hit >= 0 ? (uint32_t)hit : (fw & 3u));
-        old[i] = 0u;
-        if (in[i]) {
-            if (hit >= 0) {
-                atomicAdd(&tab[addr[i]], 1u);
-            } else if (fw < 4u) {
-                old[i] = atomicCAS(&tab[addr[i]], 0u, tag[i] | 1u);
-                pend |= 1u << i;
-            } else {
-                slow |= 1u << i;
-                b[i] += 1;  // home bucket full without the key: continue after it
-            }
-        }
+        const bool add = in[i] && hit >= 0;
+        const bool cas = in[i] && hit < 0 && fw < 4u;
+        const bool full = in[i] && hit < 0 && fw >= 4u;
+        atomicAdd(add ? &tab[addr[i]] : dummy, 1u);
+        old[i] = atomicCAS(cas ? &tab[addr[i]] : dummy, 0u, tag[i] | 1u);
+        pend |= cas ? 1u << i : 0u;
+        slow |= full ? 1u << i : 0u;
+        b[i] += full ? 1 : 0;  // home bucket full without the key: continue after it
     }
     // second pass: the swaps' results
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        if ((pend >> i) & 1u) {
-            if (old[i] != 0u) {
-                if ((old[i] & hmask) == tag[i]) atomicAdd(&tab[addr[i]], 1u);
-                else slow |= 1u << i;  // another key took the word: look again
-            }
-        }
+        const bool taken = ((pend >> i) & 1u) && old[i] != 0u;
+        const bool same = taken && (old[i] & hmask) == tag[i];
+        atomicAdd(same ? &tab[addr[i]] : dummy, 1u);
+        slow |= (taken && !same) ? 1u << i : 0u;  // another key took the word: look again
     }
     bool ok = true;
     const int32_t nb = R.limit >> 2;
@@ -329,6 +325,7 @@ struct Smem {
     int32_t *taken;      // per run: entries of the run inside the current range
     int32_t *misc;       // see kMisc*
     int2 *stack;         // ranges still to process
+    uint32_t *spare;     // one word per lane, past the table (targets of idle atomics)
     uint64_t *pool_cur;  // [next, end) of this workgroup's pool chunk
     int32_t *log_cur;    // [next, end) of this workgroup's log chunk
 };
@@ -350,7 +347,7 @@ __device__ __forceinline__ int32_t walk_lane(const int32_t *itmS, int32_t cur, i
         const int32_t j2 = (p + 2 < end) ? itmS[p + 2] : INT32_MAX;
         const int32_t j3 = (p + 3 < end) ? itmS[p + 3] : INT32_MAX;
         if (look) tab_look4(S.tab, R, j0, j1, j2, j3);
-        else ok &= tab_add4(S.tab, R, j0, j1, j2, j3);
+        else ok &= tab_add4(S.tab, S.spare, R, j0, j1, j2, j3);
         const int32_t taken = (j0 < R.hi) + (j1 < R.hi) + (j2 < R.hi) + (j3 < R.hi);
         p += taken;
         if (taken < 4) break;
@@ -465,7 +462,7 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
             }
         }
         if (look) tab_look4(S.tab, R, j[0], j[1], j[2], j[3]);
-        else ok &= tab_add4(S.tab, R, j[0], j[1], j[2], j[3]);
+        else ok &= tab_add4(S.tab, S.spare, R, j[0], j[1], j[2], j[3]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (pr[k] < 0) continue;
@@ -876,14 +873,14 @@ constexpr int kStack = 64;
 
 __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
     constexpr int LIM = kSmallSlots + kSmallPad;
-    __shared__ __align__(16) uint32_t tab[LIM];
+    __shared__ __align__(16) uint32_t tab[LIM + kWave];
     __shared__ int2 runs[kSmallRunCap];
     __shared__ int32_t taken[kSmallRunCap];
     __shared__ int2 stack[kStack];
     __shared__ int32_t misc[kMiscWave + 1];
     __shared__ uint64_t pool_cur[2];
     __shared__ int32_t log_cur[2];
-    const Smem S{tab, runs, taken, misc, stack, pool_cur, log_cur};
+    const Smem S{tab, runs, taken, misc, stack, tab + LIM, pool_cur, log_cur};
     if (threadIdx.x == 0) {
         pool_cur[0] = pool_cur[1] = 0;
         log_cur[0] = log_cur[1] = 0;
@@ -920,7 +917,7 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
 __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
     constexpr int NT = kTaskThreads;
     constexpr int LIM = kTaskSlots + kTaskPad;
-    __shared__ __align__(16) uint32_t tab[LIM];
+    __shared__ __align__(16) uint32_t tab[LIM + kWave];
     __shared__ int2 runs[kTaskRunCap];
     __shared__ int32_t taken[kTaskRunCap];
     __shared__ int2 stack[kStack];
@@ -928,7 +925,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
     __shared__ int32_t sh_task;
     __shared__ uint64_t pool_cur[2];
     __shared__ int32_t log_cur[2];
-    const Smem S{tab, runs, taken, misc, stack, pool_cur, log_cur};
+    const Smem S{tab, runs, taken, misc, stack, tab + LIM, pool_cur, log_cur};
     if (threadIdx.x == 0) {
         pool_cur[0] = pool_cur[1] = 0;
         log_cur[0] = log_cur[1] = 0;
