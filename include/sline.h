@@ -108,7 +108,7 @@ typedef struct {
     int64_t n_heavy;      /* items counted by the workgroup (multi-pass) kernel   */
     int64_t passes;       /* table passes made by the workgroup kernel            */
     /* stage times in milliseconds, filled when the build had SLINE_PROFILE  */
-    double ms_transpose;  /* row checks + transpose (scatter and row sort)        */
+    double ms_transpose;  /* row checks + transpose (radix sort by member)        */
     double ms_prepare;    /* s filter, per-item wedge counts, buckets             */
     double ms_count;      /* count pass (counting kernels, pairs per item)        */
     double ms_scan;       /* exclusive scan of pairs per item                     */

@@ -4,9 +4,9 @@
 // sline_build, stage by stage (every stage is a HIP kernel of this library):
 //   1. row_ptr check, nnz read-back                      (one host sync)
 //   2. row ids, member range / order checks
-//   3. transpose: degree histogram, scan, atomic scatter of incidence ids,
-//      per-row sort, then row ids and the position maps (one host sync for
-//      rows too long for the LDS sort)
+//   3. transpose: a stable radix sort of the (member, incidence) pairs,
+//      whose last pass writes the row ids and the position maps; the member
+//      checks are read back                              (one host sync)
 //   4. items / member lists chosen by the dual flag (H* swaps the roles, Sec. III)
 //   5. s-filtered member lists N_s(v) (degree-based pruning, Sec. IV-C) and
 //      the back-pointer of every incidence of a kept item
@@ -17,8 +17,9 @@
 //   8. output allocation, staged ranges copied to their offsets, tasks
 //      without room counted again                      (one host sync)
 // sline_build_batch runs the same stages once over many graphs (their items
-// numbered one after the other, each with its own s), sline_build_spgemm runs
-// them in product mode and filters the product.
+// numbered one after the other, each with its own s); with library-allocated
+// results, stage 8 writes every graph's pairs into that graph's own arrays.
+// sline_build_spgemm runs them in product mode and filters the product.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>

@@ -8,7 +8,9 @@
 // disjoint union of the graphs' L_s, and sorting by (a, b) keeps every
 // graph's pairs contiguous.  The kernels here build the combined item CSR
 // (checking every caller CSR on the way), give every item its graph's s,
-// and split the combined result back per graph.
+// and hand the combined result back per graph: directly, when the library
+// allocates the results (the fill writes each pair into its graph's arrays),
+// or by splitting a combined result into caller buffers.
 //
 // A dual graph's items are its vertices: their member lists are the rows of
 // H_g^T, built by transposing XD, the row concatenation of all dual graphs'

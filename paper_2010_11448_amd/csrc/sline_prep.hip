@@ -1,7 +1,7 @@
-// Preparation kernels of libsline for gfx950: CSR checks, degree histogram,
-// device-wide exclusive scans, the transpose (atomic scatter followed by a
-// per-row sort), the s-filtered membership lists, the exact per-item wedge
-// count W_a and the degree buckets.
+// Preparation kernels of libsline for gfx950: CSR checks, device-wide
+// exclusive scans, the transpose (a stable radix sort of the incidences by
+// member), the s-filtered membership lists, the exact per-item wedge count
+// W_a and the lookup-only members.
 //
 // The transpose turns the hyperedge -> vertex incidence lists into vertex ->
 // hyperedge lists (the other side of the bipartite representation, Sec. III);
