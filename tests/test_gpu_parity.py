@@ -240,6 +240,21 @@ def test_tuning_rejects_out_of_range(ctx):
     assert ctx.tuning() == base
 
 
+@pytest.mark.parametrize("n", [1, 16, 17, 256, 257, 70_000, 3_000_000])
+def test_transpose_digit_boundaries(ctx, dev, n):
+    """Member counts on both sides of the transpose's 4-bit digit boundaries
+    (one to six radix passes), duplicate rows included (n = 1), both sides."""
+    g = gen.uniform_hypergraph(300, n, 1, min(n, 12), 60 + n % 97)
+    rp, col = to_device(g, dev)
+    for dual in (0, 1):
+        for s in (1, 2):
+            print(f"case: transpose n={n} s={s} dual={dual}", flush=True)
+            L = ctx.build(rp, col, g.n_vertices, s, dual)
+            ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual,
+                                  threads=8)
+            assert_same(L, ref, f"n={n} s={s} dual={dual}")
+
+
 def test_pairs_only_flag(ctx, dev):
     """SLINE_NO_WEIGHTS: the same pairs, w neither needed nor written."""
     import torch

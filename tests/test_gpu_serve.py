@@ -95,6 +95,37 @@ def test_mixed_queries_equal_alone(dev, workers, budget):
         ctx.close()
 
 
+def test_unreleased_results_do_not_stall(dev):
+    """Results the client leaves unreleased count against the budget; with the
+    budget full of them, a query still runs when nothing else does, so every
+    query finishes although nothing is polled until the end."""
+    from paper_2010_11448_amd import sline
+
+    graphs = [gen.uniform_2000(11), gen.uniform_2000(12), gen.random_small(60, 40, 12, 7)]
+    dg = [to_device(h, dev) for h in graphs]
+    srv = sline.Server(0, hbm_budget_bytes=1 << 22, max_batch=8, workers=2)
+    ctx = sline.Context(0)
+    try:
+        ids = [srv.register(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)]
+        queries = [(g % 3, 1 + g % 4, g % 2) for g in range(24)]
+        print(f"case: serve unreleased results queries={len(queries)}", flush=True)
+        tickets = [srv.submit(ids[g], s, d) for g, s, d in queries]
+        t0 = time.time()
+        while srv.pending() != (0, 0):
+            assert time.time() - t0 < 120, "server stalled with unreleased results"
+            time.sleep(0.005)
+        for (g, s, d), t in reversed(list(zip(queries, tickets))):
+            L, info = srv.poll(t)
+            assert info["status"] == 0
+            rp, col = dg[g]
+            alone = ctx.build(rp, col, graphs[g].n_vertices, s, d)
+            assert_same(L, oracle.Pairs(alone.a.cpu().numpy(), alone.b.cpu().numpy(),
+                                        alone.w.cpu().numpy()), f"graph {g} s={s} dual={d}")
+    finally:
+        srv.close()
+        ctx.close()
+
+
 def test_server_errors(dev):
     from paper_2010_11448_amd import sline
 
