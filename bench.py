@@ -343,8 +343,8 @@ def bench_serve(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rows of the result shard across GPUs without exchange; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(rows of the result shard across GPUs without exchange)",
               file=sys.stderr)
         sys.exit(2)
     import torch
