@@ -51,6 +51,7 @@
 // fill pass that writes at the task's offset directly.  In product mode
 // (`full`, the SpGEMM companion) every b in [0, N) counts, a itself included.
 #include <algorithm>
+#include <type_traits>
 
 #include "sline_internal.h"
 
@@ -547,10 +548,13 @@ __device__ __forceinline__ bool bucket_full(const uint4 &q) {
 // at task_off[t] + rel; stage mode reserves room in the pool, writes (b, w)
 // there and logs the range (or flags task t when the pool or the log is
 // full).  Leaves the table cleared.
-template <int NT>
+template <int NT, int RUNCAP>
 __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S, const Range &R,
                                                int32_t a, int32_t sa, int32_t t, int64_t rel) {
     constexpr int W = NT / kWave;
+    // each wave lists the buckets of its block that hold pairs, in order, in
+    // the run arrays (idle during extraction): LCAP 16-bit entries per wave
+    constexpr int LCAP = (int)(RUNCAP * sizeof(int2) / sizeof(uint16_t)) / W;
     const int lane = lane_id(), wid = wave_id();
     const int32_t L = R.limit;
     const int32_t nbk = (L + 3) >> 2;  // words past L are zero
@@ -559,7 +563,9 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
     const int32_t b1 = min(nbk, b0 + per_wave);
     const uint32_t s = (uint32_t)sa;
     const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
-    int32_t mine = 0;
+    uint16_t *const lst = reinterpret_cast<uint16_t *>(S.runs) + wid * LCAP;
+    __syncthreads();  // the insertion has finished reading the run arrays
+    int32_t mine = 0, nact = 0;
     for (int32_t i = b0; i < b1; i += kWave) {
         const int32_t bk = i + lane;
         const uint4 q = bk < b1 ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
@@ -567,6 +573,10 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                           (slot_count(q.z, R) >= s) + (slot_count(q.w, R) >= s);
         mine += __popcll(__ballot(n & 1)) + 2 * __popcll(__ballot(n & 2)) +
                 4 * __popcll(__ballot(n & 4));
+        const uint64_t am = __ballot(n > 0);
+        const int32_t slot = nact + (int32_t)lanes_below(am);
+        if (n > 0 && slot < LCAP) lst[slot] = (uint16_t)bk;
+        nact += (int32_t)__popcll(am);
     }
     if (lane == 0) S.misc[kMiscWave + wid] = mine;
     __syncthreads();
@@ -644,11 +654,12 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
         }
     }
     if (write) {
-        // fullness of the bucket before this wave's block
+        // One bucket per lane (bk, valid when vb): its pairs go to
+        // run + (pairs of this wave's buckets before it).  `listed`: the
+        // lanes hold the listed buckets, not consecutive ones.
         bool prev_full = R.mul && b0 > 0 && b0 < b1 && bucket_full(t4[b0 - 1]);
-        for (int32_t i = b0; i < b1; i += kWave) {
-            const int32_t bk = i + lane;
-            const uint4 q = bk < b1 ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
+        auto emit = [&](auto listed, int32_t bk, bool vb) {
+            const uint4 q = vb ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
             const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
             uint32_t c[4];
             bool ok[4];
@@ -696,9 +707,15 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                     rank[k] = k;
                 }
                 // runs of full buckets: a bucket ends a run unless it is full
-                const bool full = bucket_full(q) && bk < b1;
-                const uint64_t fm = __ballot(full);
-                const bool pf = lane ? ((fm >> (lane - 1)) & 1ull) != 0 : prev_full;
+                const bool full = bucket_full(q) && vb;
+                bool pf;  // the bucket before this one is full
+                if (decltype(listed)::value) {
+                    pf = vb && bk > 0 && bucket_full(t4[bk - 1]);
+                } else {
+                    const uint64_t fm = __ballot(full);
+                    pf = lane ? ((fm >> (lane - 1)) & 1ull) != 0 : prev_full;
+                    prev_full = ((fm >> 63) & 1ull) != 0;
+                }
                 int32_t left = 0;
                 if (n && (full || pf)) {
                     // full buckets before this one in the same run
@@ -742,9 +759,18 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                         if (dst_w) dst_w[base + p] = (int32_t)(key[k] & R.cmask);
                     }
                 }
-                prev_full = ((fm >> 63) & 1ull) != 0;
             }
             run += step;
+        };
+        if (nact <= LCAP) {
+            // only the buckets that hold pairs, 64 at a time
+            for (int32_t i = 0; i < nact; i += kWave) {
+                const bool vb = i + lane < nact;
+                emit(std::true_type{}, vb ? (int32_t)lst[i + lane] : 0, vb);
+            }
+        } else {
+            for (int32_t i = b0; i < b1; i += kWave)
+                emit(std::false_type{}, i + lane, i + lane < b1);
         }
     }
     __syncthreads();
@@ -797,7 +823,7 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
                 insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nend, nc);
             }
             if (!split) {
-                produced += tab_extract<NT>(A, S, R, a, sa, t, produced);
+                produced += tab_extract<NT, RUNCAP>(A, S, R, a, sa, t, produced);
 #pragma unroll
                 for (int i = 0; i < kR; ++i) cur[i] = nc[i];
                 continue;
