@@ -57,11 +57,10 @@ struct Graph {
 // device, hipMalloc calls were measured at seconds each, failing or not,
 // and no worker could allocate meanwhile.  (The budget itself is kept by
 // admission, which lets a query larger than the budget run alone.)  When no
-// chunk has room,
-// chunks with nothing allocated are returned first; if that does not make
-// room the request fails at once and the library takes its fallback (a
-// smaller staging pool, or an error the worker answers by running the
-// batch's queries apart).
+// chunk has room, chunks with nothing allocated are returned first; if that
+// does not make room the request fails at once and the library takes its
+// fallback (a smaller staging pool, or an error the worker answers by
+// running the batch's queries apart).
 struct DeviceCache {
     struct Chunk {
         char *base = nullptr;
