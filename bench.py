@@ -74,13 +74,14 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
 
-def cpu_baseline(g, s_list, dual, rows_hint, budget_s=15.0):
+def cpu_baseline(g, s_list, dual, rows_hint, budget_s=20.0):
     """The O1 oracle (all pairs, sorted merge) on a seeded sample of items.
 
     Rows a are drawn uniformly; the oracle compares each with every b > a,
     so the sampled time scaled by N / rows estimates the full build.  The
-    sample size is set from a short probe so the whole sweep takes about
-    `budget_s` seconds."""
+    sample size is set from a short probe aimed at `budget_s` seconds for the
+    whole sweep; the probe overstates the cost per row somewhat (threads wait
+    for their slowest rows), so the sweep takes about 10-15 s."""
     import oracle
 
     N = g.n_vertices if dual else g.n_edges
@@ -90,7 +91,9 @@ def cpu_baseline(g, s_list, dual, rows_hint, budget_s=15.0):
     if rows_hint:
         nrows = rows_hint
     else:
-        probe = np.sort(order[:threads * 2])
+        # several rows per thread, so the probe's wall time is not set by
+        # the one slowest row of a thread
+        probe = np.sort(order[:threads * 8])
         t0 = time.perf_counter()
         oracle.naive(g.row_ptr, g.col, g.n_edges, g.n_vertices, s_list[0], dual=dual, rows=probe,
                      threads=threads, keep=False)
