@@ -54,3 +54,42 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.sline_last_stats(None, None) == sline.SLINE_EINVAL
     assert lib.sline_last_error(None) == b"no context"
     lib.sline_destroy(None)
+
+
+def test_every_entry_point_rejects_a_null_handle_without_gpu():
+    """Each declared call checks its handle and sizes before any device work."""
+    lib = sline.load()
+    E = sline.SLINE_EINVAL
+    out = sline.sline_edges()
+    csr = sline.sline_csr()
+    i32, i64 = ctypes.c_int32(0), ctypes.c_int64(0)
+    srv = ctypes.c_void_p()
+    calls = {
+        "sline_create": lambda: lib.sline_create(None, 0, None, None),
+        "sline_build": lambda: lib.sline_build(None, csr, 1, 0, 0, ctypes.byref(out)),
+        "sline_build_batch": lambda: lib.sline_build_batch(None, 1, None, None, None, 0, None),
+        "sline_build_spgemm": lambda: lib.sline_build_spgemm(None, csr, 1, 0, 0,
+                                                             ctypes.byref(out)),
+        "sline_edges_free": lambda: lib.sline_edges_free(None, ctypes.byref(out)),
+        "sline_last_stats": lambda: lib.sline_last_stats(None, None),
+        "sline_get_tuning": lambda: lib.sline_get_tuning(None, None),
+        "sline_set_tuning": lambda: lib.sline_set_tuning(None, None),
+        "sline_server_create": lambda: lib.sline_server_create(None, 0, 1 << 30, 8, 1),
+        "sline_server_register": lambda: lib.sline_server_register(None, csr, ctypes.byref(i32)),
+        "sline_server_submit": lambda: lib.sline_server_submit(None, 0, 1, 0, ctypes.byref(i64)),
+        "sline_server_poll": lambda: lib.sline_server_poll(None, 0, ctypes.byref(out), None),
+        "sline_server_release": lambda: lib.sline_server_release(None, ctypes.byref(out)),
+        "sline_server_pending": lambda: lib.sline_server_pending(None, None, None),
+    }
+    for name, call in calls.items():
+        assert call() == E, name
+    # sizes a server cannot have are refused before it touches a device
+    for budget, batch, workers in ((0, 8, 1), (1 << 30, 0, 1), (1 << 30, 8, 0), (1 << 30, 8, 17)):
+        assert lib.sline_server_create(ctypes.byref(srv), 0, budget, batch, workers) == E
+    assert lib.sline_server_last_error(None) == b"no server"
+    lib.sline_server_destroy(None)
+    lib.sline_destroy(None)
+    # every declared call is covered here or by a test above
+    covered = set(calls) | {"sline_server_last_error", "sline_server_destroy", "sline_destroy",
+                            "sline_last_error", "sline_status_str"}
+    assert set(declared_functions()) <= covered
