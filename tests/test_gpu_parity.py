@@ -131,6 +131,29 @@ def test_invalid_inputs(ctx, dev):
     bad([0, 1, 2], [0, 1], 2, s=0)            # s < 1
     bad([0, 1, 2], [0, 1], 2, dual=2)         # bad dual flag
 
+    # sizes, pointers and output buffers, through the C-ABI itself
+    rp = torch.tensor([0, 2], dtype=torch.int32, device=dev)
+    col = torch.tensor([0, 1], dtype=torch.int32, device=dev)
+    buf = torch.zeros(3, dtype=torch.int32, device=dev)
+    R, C = rp.data_ptr(), col.data_ptr()
+    lib_owned = sline.sline_edges(0, 0, None, None, None)
+    cases = [
+        ("negative n_edges", sline.sline_csr(R, C, -1, 2), lib_owned),
+        ("negative n_vertices", sline.sline_csr(R, C, 1, -1), lib_owned),
+        ("row_ptr NULL", sline.sline_csr(None, C, 1, 2), lib_owned),
+        ("col_idx NULL with members", sline.sline_csr(R, None, 1, 2), lib_owned),
+        ("members but no vertices", sline.sline_csr(R, C, 1, 0), lib_owned),
+        ("negative capacity", sline.sline_csr(R, C, 1, 2), sline.sline_edges(0, -1, None, None, None)),
+        ("capacity without buffers", sline.sline_csr(R, C, 1, 2),
+         sline.sline_edges(0, 1, buf.data_ptr(), None, None)),
+    ]
+    for what, H, out in cases:
+        print(f"case: invalid {what}", flush=True)
+        assert sline.sline_build(ctx.ctx, H, 1, 0, 0, out) == sline.SLINE_EINVAL, what
+    # the context still builds after every refusal
+    g = gen.from_sets([[0, 1], [1, 2], [0, 1, 2]], 3)
+    _check(ctx, dev, g, 1, 0, "after invalid inputs")
+
 
 def test_capacity_protocol(ctx, dev):
     """ECAPACITY reports the size and a retry writes the same result."""
