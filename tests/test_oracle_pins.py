@@ -69,6 +69,22 @@ def test_o1_equals_blas_product_on_tiny_graphs(m, n, p, seed, s):
         check_against_dense(g, s, dual)
 
 
+@settings(max_examples=60, deadline=None)
+@given(st.integers(0, 30), st.integers(1, 30), st.floats(0.0, 0.6), st.integers(0, 2**31 - 1),
+       st.integers(1, 5), st.integers(1, 4))
+def test_o3_equals_blas_product_on_tiny_graphs(m, n, p, seed, s, threads):
+    """O3 pinned to the dense product directly, not through O1."""
+    rng = np.random.default_rng(seed)
+    B = (rng.random((m, n)) < p).astype(np.int64)
+    g = csr_from_dense(B)
+    for dual in (0, 1):
+        Wm = (B.T @ B) if dual else (B @ B.T)
+        a, b, w = pairs_from_dense(Wm, s)
+        got, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual,
+                              threads=threads)
+        assert np.array_equal(got.a, a) and np.array_equal(got.b, b) and np.array_equal(got.w, w)
+
+
 @pytest.mark.parametrize("seed", gen.UNIFORM_SEEDS)
 def test_o1_equals_blas_product_on_uniform_2000(seed):
     g = gen.uniform_2000(seed)
