@@ -81,7 +81,7 @@ def cpu_baseline(g, s_list, dual, rows_hint, budget_s=20.0):
     so the sampled time scaled by N / rows estimates the full build.  The
     sample size is set from a short probe aimed at `budget_s` seconds for the
     whole sweep; the probe overstates the cost per row somewhat (threads wait
-    for their slowest rows), so the sweep takes about 10-15 s."""
+    for their slowest rows), so the sweep takes about 10-20 s."""
     import oracle
 
     N = g.n_vertices if dual else g.n_edges
