@@ -245,8 +245,12 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
                                  int32_t max_batch, int32_t n_workers);
 
 /* Register a hypergraph (device CSR as in sline_build, caller-owned) and get
- * its id.  Reads the CSR once to size queries; SLINE_EINVAL if a member id
- * is out of range. */
+ * its id.  Reads the CSR once to size queries and checks it against the rules
+ * of sline_csr (row_ptr[0] = 0, row_ptr non-decreasing, members
+ * in range and strictly increasing within a row): SLINE_EINVAL if it breaks
+ * one, so a malformed graph never joins a batch.  (A batch that still fails
+ * with SLINE_EINVAL or SLINE_ENOMEM is run again one query at a time, so
+ * every query gets the status of its own plain build.) */
 sline_status sline_server_register(sline_server *srv, sline_csr H, int32_t *graph_id);
 
 /* Queue the query L_s of graph `graph_id` (dual as in sline_build). */

@@ -177,10 +177,34 @@ def naive(row_ptr, col, n_edges: int, n_vertices: int, s: int, dual: int = 0,
     return _finish(rc, pairs, st, keep)
 
 
+@dataclass
+class Prepared:
+    """Item lists and member lists of one side of a hypergraph, built once
+    (the oracle's own counting-sort transpose) for many ``wedge`` calls."""
+
+    rp: np.ndarray
+    col: np.ndarray
+    N: int
+    rpT: np.ndarray
+    colT: np.ndarray
+
+
+def prepare(row_ptr, col, n_edges: int, n_vertices: int, dual: int = 0) -> Prepared:
+    """The lists ``wedge`` walks for this side, for reuse across calls."""
+    return Prepared(*_items(row_ptr, col, n_edges, n_vertices, dual))
+
+
 def wedge(row_ptr, col, n_edges: int, n_vertices: int, s: int, dual: int = 0,
-          rows=None, threads: int = 1, keep: bool = True):
-    """O3: wedge counting over shared members with exact counters."""
-    rp, cl, N, rpT, colT = _items(row_ptr, col, n_edges, n_vertices, dual)
+          rows=None, threads: int = 1, keep: bool = True, prepared: Prepared | None = None):
+    """O3: wedge counting over shared members with exact counters.
+
+    ``prepared`` (from ``prepare`` on the same graph and side) skips building
+    the lists again; the graph arguments are then ignored."""
+    if prepared is not None:
+        rp, cl, N, rpT, colT = (prepared.rp, prepared.col, prepared.N, prepared.rpT,
+                                prepared.colT)
+    else:
+        rp, cl, N, rpT, colT = _items(row_ptr, col, n_edges, n_vertices, dual)
     r, nr = _rows_arg(rows)
     pairs, st = _Pairs(), _Stats()
     rc = _load().oracle_wedge_rows(_ptr(rp), _ptr(cl), _ptr(rpT), _ptr(colT), N, s, _ptr(r), nr,

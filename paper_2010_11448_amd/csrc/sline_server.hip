@@ -347,10 +347,12 @@ void worker_loop(sline_server *S, int wi) {
                                             outs.data());
         // per query: the batch's status, or its own when the batch ran apart
         std::vector<sline_status> qst(G, st);
-        const bool apart = st == SLINE_ENOMEM && G > 1;
+        const bool apart = (st == SLINE_ENOMEM || st == SLINE_EINVAL) && G > 1;
         if (apart) {
-            // device memory ran short for the batch as a whole: run its
-            // queries one at a time (a single graph needs no combined output)
+            // device memory ran short for the batch as a whole, or one of its
+            // graphs was refused: run its queries one at a time (a single
+            // graph needs no combined output), so that each query gets the
+            // status of its own plain build
             for (int32_t g = 0; g < G; ++g) {
                 outs[g] = sline_edges{};
                 qst[g] = sline_build_batch(W.ctx, 1, &Hs[g], &ss[g], &ds[g], flags, &outs[g]);
@@ -478,7 +480,10 @@ sline_status sline_server_register(sline_server *S, sline_csr H, int32_t *graph_
         return SLINE_EDEVICE;
     }
     g.nnz = rp.back();
-    if (g.nnz < 0 || (g.nnz > 0 && (!H.col_idx || H.n_vertices == 0))) return SLINE_EINVAL;
+    // the full CSR rules of sline_build, so that a malformed graph is refused
+    // here rather than failing every batch its queries would join
+    if (rp[0] != 0 || g.nnz < 0 || (g.nnz > 0 && (!H.col_idx || H.n_vertices == 0)))
+        return SLINE_EINVAL;
     for (int32_t e = 0; e < H.n_edges; ++e) {
         const double k = rp[e + 1] - rp[e];
         if (k < 0) return SLINE_EINVAL;
@@ -492,9 +497,13 @@ sline_status sline_server_register(sline_server *S, sline_csr H, int32_t *graph_
             return SLINE_EDEVICE;
         }
         std::vector<int32_t> deg((size_t)H.n_vertices, 0);
-        for (int32_t v : col) {
-            if (v < 0 || v >= H.n_vertices) return SLINE_EINVAL;
-            deg[v] += 1;
+        for (int32_t e = 0; e < H.n_edges; ++e) {
+            for (int32_t k = rp[e]; k < rp[e + 1]; ++k) {
+                const int32_t v = col[k];
+                if (v < 0 || v >= H.n_vertices) return SLINE_EINVAL;
+                if (k > rp[e] && v <= col[k - 1]) return SLINE_EINVAL;  // rows are sets, ascending
+                deg[v] += 1;
+            }
         }
         for (int32_t d : deg) g.w1[0] += (double)d * (d - 1) / 2;
     }

@@ -1,15 +1,29 @@
 """Full-size parity on the 1,000,000 x 2,000,000 power-law workload and its
-dual, in the launch configuration the bench times.
+dual, in the launch configuration the bench times (one plain sline_build per
+s), against O3 (the wedge oracle, Sec. IV-B with exact counters) over EVERY
+row of the result.
 
-The oracle cannot produce the whole result at this size in seconds, so the
-checks are: every output row of a seeded sample of items equals the oracle's
-row (O3 restricted to those items), the whole output is canonical (a < b,
-w >= s, strictly increasing (a, b)), the wedge count equals its closed form
-sum_v C(d_s(v), 2), and for s = 1 the weights sum to that same number (each
-wedge adds one to exactly one pair).
+The items are cut into contiguous row ranges holding about the same number of
+output pairs; for each range the oracle computes exactly those rows and the
+GPU's slice of the same rows is compared with it:
+
+* s >= 2: element by element (a, b and w of every pair);
+* s = 1 (7.0e9 pairs, 84 GB): per range, the pair count, the weight sum and
+  the order-independent 64-bit digest of the (a, b, w) triples; element by
+  element on the 100 items with the most wedges and on three whole ranges
+  drawn at random.  With the canonical-order check of the whole output this
+  pins the result as a set.
+
+The whole output is also checked for canonical order (a < b, w >= s, (a, b)
+strictly increasing), the wedge count against its closed form
+sum_v C(d_s(v), 2), and at s = 1 the weights against the same sum (each wedge
+adds one to exactly one pair).  Definition followed: Sec. III.
 """
 
 from __future__ import annotations
+
+import os
+import time
 
 import numpy as np
 import pytest
@@ -17,14 +31,23 @@ import pytest
 import oracle
 from paper_2010_11448_amd import gen
 
-from helpers import check_canonical_torch, to_device
+from helpers import check_canonical_torch, digest_torch, to_device
 
 pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+CASES = [(1, 0), (2, 0), (4, 0), (8, 0), (16, 0), (2, 1), (8, 1), (32, 1)]
 
 
 @pytest.fixture(scope="module")
 def graph():
     return gen.powerlaw_1m()
+
+
+@pytest.fixture(scope="module")
+def prepared(graph):
+    g = graph
+    return {d: oracle.prepare(g.row_ptr, g.col, g.n_edges, g.n_vertices, dual=d) for d in (0, 1)}
 
 
 def _wedges_closed_form(g, s, dual):
@@ -43,12 +66,56 @@ def _wedges_closed_form(g, s, dual):
     return int((d * (d - 1) // 2).sum())
 
 
-@pytest.mark.parametrize("s,dual", [(1, 0), (2, 0), (16, 0), (2, 1), (32, 1)])
-def test_fullsize_sampled_rows(graph, s, dual):
+def _wedges_per_item(P):
+    """W_a at s = 1: for every member list N(v) (ascending items), the item at
+    rank r has d(v) - 1 - r later items in it."""
+    deg = np.diff(P.rpT).astype(np.int64)
+    nnz = int(P.rpT[-1])
+    owner = np.repeat(np.arange(len(deg)), deg)
+    rank = np.arange(nnz, dtype=np.int64) - P.rpT[:-1].astype(np.int64)[owner]
+    return np.bincount(P.colT[:nnz], weights=(deg[owner] - 1 - rank), minlength=P.N)
+
+
+def _ranges(L, N, parts):
+    """Item boundaries 0 = r_0 < r_1 < ... < r_k = N cutting the output into
+    about `parts` pieces of equal pair counts."""
+    import torch
+
+    n = int(L.a.shape[0])
+    cuts = [0, N]
+    if n:
+        pos = torch.linspace(0, n - 1, parts + 1, device=L.a.device).long()[1:-1]
+        cuts += L.a[pos].cpu().tolist()
+    return sorted(set(int(x) for x in cuts))
+
+
+def _slice(L, lo_item, hi_item):
+    import torch
+
+    keys = torch.tensor([lo_item, hi_item], dtype=torch.int32, device=L.a.device)
+    lo, hi = torch.searchsorted(L.a, keys, side="left").cpu().tolist()
+    return lo, hi
+
+
+def _compare_rows(L, ref, lo, hi, what):
+    n = hi - lo
+    assert n == len(ref.a), f"{what}: {n} pairs vs oracle {len(ref.a)}"
+    for got, want, name in ((L.a, ref.a, "a"), (L.b, ref.b, "b"), (L.w, ref.w, "w")):
+        g = got[lo:hi].cpu().numpy()
+        if not np.array_equal(g, want):
+            bad = int(np.flatnonzero(g != want)[0])
+            raise AssertionError(f"{what}: {name} differs first at pair {lo + bad}: "
+                                 f"got {int(g[bad])} want {int(want[bad])}")
+
+
+@pytest.mark.parametrize("s,dual", CASES)
+def test_fullsize_every_row(graph, prepared, s, dual):
     import torch
     from paper_2010_11448_amd import sline
 
     g = graph
+    P = prepared[dual]
+    N = P.N
     dev = torch.device("cuda", 0)
     print(f"case: full size powerlaw s={s} dual={dual}", flush=True)
     rp, col = to_device(g, dev)
@@ -63,20 +130,38 @@ def test_fullsize_sampled_rows(graph, s, dual):
     assert st["wedges"] == W
     if s == 1:
         assert int(L.w.to(torch.int64).sum().item()) == W
-    N = g.n_vertices if dual else g.n_edges
-    rng = np.random.default_rng(1000 + s + 7 * dual)
-    rows = np.sort(rng.choice(N, size=48, replace=False)).astype(np.int32)
-    ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual, rows=rows,
-                          threads=8)
-    keys = torch.from_numpy(rows.astype(np.int32)).to(dev)
-    lo = torch.searchsorted(L.a, keys, side="left").cpu().numpy()
-    hi = torch.searchsorted(L.a, keys, side="right").cpu().numpy()
-    ra = np.asarray(ref.a)
-    for i, a in enumerate(rows.tolist()):
-        sel = ra == a
-        got_b = L.b[int(lo[i]):int(hi[i])].cpu().numpy()
-        got_w = L.w[int(lo[i]):int(hi[i])].cpu().numpy()
-        assert np.array_equal(got_b, np.asarray(ref.b)[sel]), f"row {a} s={s} dual={dual}: b"
-        assert np.array_equal(got_w, np.asarray(ref.w)[sel]), f"row {a} s={s} dual={dual}: w"
+    t0 = time.time()
+    cuts = _ranges(L, N, 64 if s == 1 else 32)
+    rng = np.random.default_rng(7000 + s + 31 * dual)
+    full_ranges = set(rng.choice(len(cuts) - 1, size=min(3, len(cuts) - 1), replace=False).tolist())
+    total = 0
+    for k in range(len(cuts) - 1):
+        lo_item, hi_item = cuts[k], cuts[k + 1]
+        rows = np.arange(lo_item, hi_item, dtype=np.int32)
+        lo, hi = _slice(L, lo_item, hi_item)
+        what = f"s={s} dual={dual} rows [{lo_item}, {hi_item})"
+        elementwise = s > 1 or k in full_ranges
+        ref, ost = oracle.wedge(None, None, 0, 0, s, rows=rows, threads=THREADS,
+                                keep=elementwise, prepared=P)
+        if elementwise:
+            _compare_rows(L, ref, lo, hi, what)
+        else:
+            assert hi - lo == ost.n_pairs, f"{what}: {hi - lo} pairs vs oracle {ost.n_pairs}"
+            assert int(L.w[lo:hi].to(torch.int64).sum().item()) == ost.sum_w, f"{what}: sum w"
+            assert digest_torch(L.a[lo:hi], L.b[lo:hi], L.w[lo:hi]) == ost.digest, f"{what}: digest"
+        total += ost.n_pairs
+    assert total == len(L)
+    if s == 1:
+        # element by element on the heaviest items as well
+        top = np.sort(np.argsort(_wedges_per_item(P), kind="stable")[-100:]).astype(np.int32)
+        ref, _ = oracle.wedge(None, None, 0, 0, s, rows=top, threads=THREADS, prepared=P)
+        ra = np.asarray(ref.a)
+        for a in top.tolist():
+            lo, hi = _slice(L, a, a + 1)
+            sel = ra == a
+            _compare_rows(L, oracle.Pairs(ra[sel], np.asarray(ref.b)[sel], np.asarray(ref.w)[sel]),
+                          lo, hi, f"s=1 dual={dual} heavy row {a}")
+    print(f"case: full size powerlaw s={s} dual={dual}: {len(L)} pairs over {len(cuts) - 1} "
+          f"ranges checked in {time.time() - t0:.1f} s", flush=True)
     del L
     torch.cuda.empty_cache()

@@ -146,3 +146,93 @@ def test_server_errors(dev):
         assert srv.pending() == (0, 0)
     finally:
         srv.close()
+
+
+def test_malformed_graphs_refused_at_registration(dev):
+    """A graph that breaks the CSR rules is refused when it is registered, so
+    it can never join (and fail) a batch; valid queries submitted afterwards
+    still equal their plain builds."""
+    import numpy as np
+    import torch
+    from paper_2010_11448_amd import sline
+
+    good = gen.uniform_2000(13)
+    bad_sets = {
+        "row_ptr[0] != 0": (np.array([1, 3, 5], np.int32), np.array([0, 1, 2, 3, 4], np.int32)),
+        "unsorted row": (np.array([0, 3, 5], np.int32), np.array([2, 1, 3, 0, 4], np.int32)),
+        "repeated member": (np.array([0, 3, 5], np.int32), np.array([1, 1, 3, 0, 4], np.int32)),
+        "member out of range": (np.array([0, 2, 4], np.int32), np.array([0, 9, 1, 2], np.int32)),
+        "row_ptr decreases": (np.array([0, 4, 2, 5], np.int32),
+                              np.array([0, 1, 2, 3, 4], np.int32)),
+    }
+    srv = sline.Server(0, hbm_budget_bytes=1 << 30, max_batch=16, workers=2)
+    ctx = sline.Context(0)
+    try:
+        rp, col = to_device(good, dev)
+        gid = srv.register(rp, col, good.n_vertices)
+        keep = []
+        for what, (brp, bcol) in bad_sets.items():
+            print(f"case: serve register refuses {what}", flush=True)
+            drp = torch.from_numpy(brp).to(dev)
+            dcol = torch.from_numpy(bcol).to(dev)
+            keep.append((drp, dcol))
+            with pytest.raises(sline.SlineError) as ei:
+                srv.register(drp, dcol, 5)
+            assert ei.value.status == sline.SLINE_EINVAL, what
+        tickets = [(srv.submit(gid, s_, d_), s_, d_) for s_ in (1, 2, 3) for d_ in (0, 1)]
+        done = _drain(srv, [t for t, _, _ in tickets])
+        for t, s_, d_ in tickets:
+            L, info = done[t]
+            assert info["status"] == 0
+            alone = ctx.build(rp, col, good.n_vertices, s_, d_)
+            assert_same(L, oracle.Pairs(alone.a.cpu().numpy(), alone.b.cpu().numpy(),
+                                        alone.w.cpu().numpy()), f"s={s_} dual={d_}")
+    finally:
+        srv.close()
+        ctx.close()
+
+
+def test_fullsize_queries_in_the_mix(dev):
+    """Queries on the 1,000,000 x 2,000,000 power-law graph (s = 2 and 16, both
+    sides) submitted together with small queries: each served result equals
+    the plain build of the same query, compared element by element on the
+    device (the plain build itself is checked against the oracle at this size
+    in test_gpu_fullsize.py)."""
+    import torch
+    from paper_2010_11448_amd import sline
+
+    big = gen.powerlaw_1m()
+    small = [gen.uniform_2000(11), gen.batch_graph(3).graph, gen.batch_graph(9).graph]
+    dbig = to_device(big, dev)
+    dsmall = [to_device(h, dev) for h in small]
+    srv = sline.Server(0, hbm_budget_bytes=96 << 30, max_batch=16, workers=3)
+    ctx = sline.Context(0)
+    try:
+        gbig = srv.register(dbig[0], dbig[1], big.n_vertices)
+        gsm = [srv.register(rp, col, h.n_vertices) for (rp, col), h in zip(dsmall, small)]
+        queries = []
+        for s_, d_ in ((2, 0), (16, 0), (2, 1), (16, 1)):
+            queries.append((None, s_, d_))
+            for i in range(len(small)):
+                queries.append((i, 1 + (s_ + i) % 5, (d_ + i) % 2))
+        print(f"case: serve full-size power-law queries in a mix of {len(queries)}", flush=True)
+        tickets = [srv.submit(gbig if g is None else gsm[g], s_, d_) for g, s_, d_ in queries]
+        done = _drain(srv, tickets, timeout_s=300.0)
+        for (g, s_, d_), t in zip(queries, tickets):
+            L, info = done[t]
+            assert info["status"] == 0
+            if g is None:
+                rp, col, nv, what = dbig[0], dbig[1], big.n_vertices, f"full size s={s_} dual={d_}"
+            else:
+                (rp, col), nv = dsmall[g], small[g].n_vertices
+                what = f"small graph {g} s={s_} dual={d_}"
+            alone = ctx.build(rp, col, nv, s_, d_)
+            assert len(L) == len(alone), what
+            for x, y, name in ((L.a, alone.a, "a"), (L.b, alone.b, "b"), (L.w, alone.w, "w")):
+                assert torch.equal(x, y), f"{what}: {name} differs from the plain build"
+            del L, alone
+            done[t] = None
+            torch.cuda.empty_cache()
+    finally:
+        srv.close()
+        ctx.close()
