@@ -170,6 +170,36 @@ void sline_destroy(sline_ctx *ctx);
 sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
                          uint32_t flags, sline_edges *out);
 
+/* Size of the device scratch array of sline_build_noalloc (bytes, per
+ * device).  The library holds it on every device it runs on until the
+ * process ends. */
+#define SLINE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sline_build
+ * with caller buffers and no allocation or free of any kind.  Every device
+ * buffer of the build (CSR checks, transpose, filtered lists, task arrays,
+ * staging pool) is carved from a fixed device array of
+ * SLINE_NOALLOC_SCRATCH_BYTES that the library keeps per device; the staging
+ * pool takes whatever the rest leaves, and tasks that find no room in it are
+ * counted again straight into the caller's arrays.
+ *   out    caller buffers only: capacity > 0 and a, b (and w unless
+ *          SLINE_NO_WEIGHTS) non-NULL, else SLINE_EINVAL.  On success the
+ *          result is exactly sline_build's.  If the result needs more than
+ *          `capacity` entries the call returns SLINE_ECAPACITY with n_pairs
+ *          set and writes nothing else; a retry counts again (the scratch
+ *          keeps no work between calls).
+ * Arguments, result and other errors as in sline_build, plus SLINE_ENOMEM
+ * (with a message naming the bytes needed) when the build's buffers do not
+ * fit the scratch array: about 45 bytes per incidence, 30 per item and 60
+ * per counting task, so hypergraphs up to a few 10^5 items and about 10^6
+ * incidences fit.  The scratch array is shared by every call on a device:
+ * calls on one device that overlap in time (several host threads, or
+ * contexts on different streams) race on it and must be serialized by the
+ * caller.  Every call clears what it needs zeroed. */
+sline_status sline_build_noalloc(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
+                                 uint32_t flags, sline_edges *out);
+
 /* Companion route to the same result (Sec. IV-D): the product C = H H^T
  * (H* H*^T for dual = 1) with both triangles and the diagonal, computed row
  * by row (Gustavson) with the LDS hash accumulators of sline_build and

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,42 @@
 #include "sline_internal.h"
 
 using namespace sl;
+
+// Device scratch of sline_build_noalloc: the whole workspace of one build
+// (CSR checks, transpose, filtered lists, task arrays, staging pool), so that
+// the entry point never allocates.  Each device holds its own copy from the
+// moment the library's code object is loaded on it until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host it only
+// names the symbol): it uses the device address taken once per device by
+// scratch_address().
+static __device__ __align__(256) unsigned char scratch[SLINE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (sline_create calls this).  Null if the lookup failed.
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        } else {
+            g_scratch_ptr[device] = p;
+        }
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
 
 struct sline_ctx {
     int device = 0;
@@ -88,6 +125,16 @@ struct sline_ctx {
         sline_edges *outs = nullptr;
         bool done = false;  // the fill handed the outputs over
     } direct;
+    // sline_build_noalloc: while `base` is set, the workspace, the task arrays
+    // and the staging pool are carved from this fixed device region (the
+    // device's scratch array) instead of being allocated; `used` is the end
+    // of what the current build has taken.
+    struct Fixed {
+        char *base = nullptr;
+        size_t size = 0;
+        size_t used = 0;
+    } fixed;
+    bool pool_fixed = false;  // c->pool lies in the fixed region: never freed
 };
 
 namespace {
@@ -143,7 +190,32 @@ struct Arena {
     }
 };
 
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Fixed-region mode: the next `bytes` of the region, or SLINE_ENOMEM with the
+// size the build needs when the region is too small.
+char *fixed_take(sline_ctx *c, size_t from, size_t bytes, const char *what) {
+    const size_t at = align256(from);
+    if (at + bytes > c->fixed.size) {
+        char buf[256];
+        snprintf(buf, sizeof buf,
+                 "sline_build_noalloc: %s needs %zu bytes of scratch at offset %zu; "
+                 "the scratch holds %zu bytes",
+                 what, bytes, at, c->fixed.size);
+        c->last_error = buf;
+        throw Fail{SLINE_ENOMEM};
+    }
+    c->fixed.used = at + bytes;
+    return c->fixed.base + at;
+}
+
 void ensure_ws(sline_ctx *c, size_t bytes) {
+    if (c->fixed.base) {
+        // the workspace starts the region; the task arrays and the pool follow it
+        c->ws = fixed_take(c, 0, bytes, "the workspace");
+        c->ws_bytes = bytes;
+        return;
+    }
     if (c->ws_bytes >= bytes) return;
     if (c->ws) {
         hip_check(c, hipStreamSynchronize(c->stream), "workspace release");
@@ -163,6 +235,13 @@ void ensure_ws(sline_ctx *c, size_t bytes) {
 void sync(sline_ctx *c, const char *where) { hip_check(c, hipStreamSynchronize(c->stream), where); }
 
 void release_pool(sline_ctx *c) {
+    if (c->pool_fixed) {
+        // a pool inside the fixed region is not the allocator's to free
+        c->pool = nullptr;
+        c->pool_bytes = 0;
+        c->pool_fixed = false;
+        return;
+    }
     if (!c->pool) return;
     (void)hipStreamSynchronize(c->stream);
     dev_free(c, c->pool, c->pool_bytes);
@@ -176,6 +255,19 @@ void release_pool(sline_ctx *c) {
 int64_t acquire_pool(sline_ctx *c, int64_t want, int64_t pair_bytes) {
     release_pool(c);
     int64_t cap = std::min<int64_t>(want, c->tune.stage_max_bytes / pair_bytes);
+    if (c->fixed.base) {
+        // whatever the fixed region has left after the task arrays (tasks
+        // that find no room are counted again in the fill pass)
+        const size_t at = align256(c->fixed.used);
+        const int64_t room = at < c->fixed.size ? (int64_t)((c->fixed.size - at) / pair_bytes) : 0;
+        cap = std::min<int64_t>(cap, room);
+        if (cap < 256) return 0;
+        c->pool = c->fixed.base + at;
+        c->pool_bytes = (size_t)(cap * pair_bytes);
+        c->pool_fixed = true;
+        c->fixed.used = at + c->pool_bytes;
+        return cap;
+    }
     while (cap >= (1 << 20)) {
         void *p = dev_alloc(c, (size_t)(cap * pair_bytes));
         if (p) {
@@ -284,6 +376,11 @@ TaskLayout plan_tasks(Arena &A, int64_t T) {
 }
 
 void ensure_ws2(sline_ctx *c, size_t bytes) {
+    if (c->fixed.base) {
+        c->ws2 = fixed_take(c, c->ws_bytes, bytes, "the task arrays");
+        c->ws2_bytes = bytes;
+        return;
+    }
     if (c->ws2_bytes >= bytes) return;
     if (c->ws2) {
         hip_check(c, hipStreamSynchronize(c->stream), "workspace release");
@@ -518,6 +615,62 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     ItemS IS;
     IS.s_min = IS.s_max = s;
     return build_core(c, H, s, dual, flags, out, IS);
+}
+
+// sline_build into caller buffers with every device buffer of the build
+// carved from this device's scratch array: no allocation, no free.  The
+// context's own workspace and any staging pool kept for a capacity retry are
+// set aside and put back afterwards untouched.
+sline_status noalloc_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual,
+                          uint32_t flags, sline_edges *out) {
+    if (!out) {
+        set_err(c, "out is NULL");
+        return SLINE_EINVAL;
+    }
+    if (s < 1 || (dual != 0 && dual != 1) || H.n_edges < 0 || H.n_vertices < 0) {
+        set_err(c, "invalid argument (s >= 1, dual in {0,1}, sizes >= 0 required)");
+        return SLINE_EINVAL;
+    }
+    if (out->capacity <= 0 || !out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))) {
+        set_err(c, "sline_build_noalloc writes into caller buffers only: capacity > 0 and a, b "
+                   "and (without SLINE_NO_WEIGHTS) w are required");
+        return SLINE_EINVAL;
+    }
+    void *base = scratch_address(c->device);
+    if (!base) {
+        set_err(c, "the device address of the scratch array could not be taken");
+        return SLINE_EDEVICE;
+    }
+    // a pending capacity retry of sline_build refers to buffers this call reuses
+    c->pending.valid = false;
+    struct Saved {
+        sline_ctx *c;
+        void *ws, *ws2, *pool;
+        size_t ws_bytes, ws2_bytes, pool_bytes;
+        ~Saved() {
+            c->fixed = sline_ctx::Fixed{};
+            c->pool_fixed = false;
+            c->ws = ws;
+            c->ws_bytes = ws_bytes;
+            c->ws2 = ws2;
+            c->ws2_bytes = ws2_bytes;
+            c->pool = pool;
+            c->pool_bytes = pool_bytes;
+        }
+    } saved{c, c->ws, c->ws2, c->pool, c->ws_bytes, c->ws2_bytes, c->pool_bytes};
+    c->pool = nullptr;
+    c->pool_bytes = 0;
+    c->pool_fixed = false;
+    c->fixed.base = static_cast<char *>(base);
+    c->fixed.size = SLINE_NOALLOC_SCRATCH_BYTES;
+    c->fixed.used = 0;
+    ItemS IS;
+    IS.s_min = IS.s_max = s;
+    const sline_status r = build_core(c, H, s, dual, flags, out, IS);
+    // the counted work lives in the scratch array, which the next call reuses
+    c->pending.valid = false;
+    release_pool(c);
+    return r;
 }
 
 sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
@@ -1284,6 +1437,9 @@ sline_status sline_create(sline_ctx **ctx, int device, void *hip_stream, const s
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->n_cu = ncu;
+    // set-up of sline_build_noalloc: this device's address of the scratch
+    // array (a failure is reported by that entry point, not here)
+    (void)scratch_address(device);
     if (hipHostMalloc((void **)&c->host, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
@@ -1332,6 +1488,27 @@ sline_status sline_build(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uin
     } catch (const std::bad_alloc &) {
         c->pending.valid = false;
         release_pool(c);
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_build_noalloc(sline_ctx *c, sline_csr H, int32_t s, int32_t dual,
+                                 uint32_t flags, sline_edges *out) {
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return noalloc_impl(c, H, s, dual, flags, out);
+    } catch (const Fail &f) {
+        c->pending.valid = false;
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        c->pending.valid = false;
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;
     }

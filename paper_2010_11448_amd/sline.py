@@ -100,6 +100,9 @@ SIGNATURES = {
     "sline_build_spgemm": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_uint32,
                                             ctypes.POINTER(sline_edges)]),
+    "sline_build_noalloc": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_uint32,
+                                             ctypes.POINTER(sline_edges)]),
     "sline_build_batch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sline_csr),
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
@@ -166,6 +169,11 @@ def sline_destroy(ctx) -> None:
 
 def sline_build(ctx, csr: sline_csr, s: int, dual: int, flags: int, out: sline_edges) -> int:
     return load().sline_build(ctx, csr, s, dual, flags, ctypes.byref(out))
+
+
+def sline_build_noalloc(ctx, csr: sline_csr, s: int, dual: int, flags: int,
+                        out: sline_edges) -> int:
+    return load().sline_build_noalloc(ctx, csr, s, dual, flags, ctypes.byref(out))
 
 
 def sline_build_batch(ctx, csrs, s, dual, flags: int, outs) -> int:
@@ -300,6 +308,18 @@ class Context:
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
         return LineGraph(a, b, w)
+
+    def build_noalloc(self, row_ptr, col, n_vertices: int, s: int, dual: int = 0,
+                      flags: int = 0, a=None, b=None, w=None):
+        """sline_build_noalloc into the caller's int32 device tensors a, b, w
+        (equal lengths; w may be None with SLINE_NO_WEIGHTS).  Returns
+        (status, n_pairs); on SLINE_OK the first n_pairs entries hold L_s."""
+        cap = int(a.numel())
+        out = sline_edges(0, cap, a.data_ptr(), b.data_ptr(),
+                          None if w is None else w.data_ptr())
+        st = sline_build_noalloc(self.ctx, self.csr(row_ptr, col, n_vertices), s, dual, flags,
+                                 out)
+        return st, int(out.n_pairs)
 
     def build_owned(self, row_ptr, col, n_vertices: int, s: int, dual: int = 0,
                     flags: int = 0) -> sline_edges:

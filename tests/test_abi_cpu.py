@@ -67,6 +67,8 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
     calls = {
         "sline_create": lambda: lib.sline_create(None, 0, None, None),
         "sline_build": lambda: lib.sline_build(None, csr, 1, 0, 0, ctypes.byref(out)),
+        "sline_build_noalloc": lambda: lib.sline_build_noalloc(None, csr, 1, 0, 0,
+                                                               ctypes.byref(out)),
         "sline_build_batch": lambda: lib.sline_build_batch(None, 1, None, None, None, 0, None),
         "sline_build_spgemm": lambda: lib.sline_build_spgemm(None, csr, 1, 0, 0,
                                                              ctypes.byref(out)),
