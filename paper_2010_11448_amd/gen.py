@@ -257,6 +257,7 @@ def batch_graph(g: int, seed: int = BATCH_SEED, m_cap: int | None = None) -> Bat
     hg = zipf_uniform_hypergraph(mg, 2 * mg, 2.2, 2, 2000, gs)
     hg.meta["workload"] = "batch_lognormal"
     hg.meta["index"] = g
+    hg.meta["s"] = s
     return BatchItem(hg, s, 0)
 
 
@@ -357,3 +358,36 @@ def random_small(m: int, n: int, max_size: int, seed: int, p_empty: float = 0.1)
         pick = np.argsort(st.uniform(n), kind="stable")[:k]
         sets.append(pick.tolist())
     return from_sets(sets, n)
+
+
+# ------------------------------------------------- parallel generation
+
+def make(kind: str, *args, **kw) -> Hypergraph:
+    """A workload graph by name: ``powerlaw_1m``, ``batch_graph`` (its
+    Hypergraph only), ``uniform_2000``."""
+    if kind == "powerlaw_1m":
+        return powerlaw_1m(*args, **kw)
+    if kind == "batch_graph":
+        return batch_graph(*args, **kw).graph
+    if kind == "uniform_2000":
+        return uniform_2000(*args, **kw)
+    raise ValueError(kind)
+
+
+def _make_spec(spec):
+    kind, args, kw = spec
+    return make(kind, *args, **kw)
+
+
+def make_many(specs: list, workers: int = 1) -> list[Hypergraph]:
+    """``make`` over (kind, args, kwargs) specs, in fresh worker processes when
+    ``workers`` > 1 (every draw is seeded per graph, so the result does not
+    depend on the number of workers).  Call it before the process touches a
+    GPU: the workers are started with ``spawn``."""
+    if workers <= 1 or len(specs) <= 1:
+        return [_make_spec(s) for s in specs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_make_spec, specs, chunksize=max(1, len(specs) // (4 * workers))))
