@@ -138,7 +138,11 @@ typedef struct {
  *   task_grid_per_cu   resident task workgroups per CU (1..16)
  *   stage_max_bytes    cap of the staging pool that lets one counting pass
  *                      produce the result; tasks that do not fit are counted
- *                      again (>= 0; 0 = always two passes) */
+ *                      again (>= 0; 0 = always two passes)
+ *   dense_min_wedges   an item whose candidates give at least this many
+ *                      wedges per sub-range narrow enough for direct
+ *                      (unhashed) counters is cut into such sub-ranges
+ *                      (0..2^24; 0 = sub-ranges by wedge count only) */
 typedef struct {
     int32_t small_max_wedges;
     int32_t task_wedges;
@@ -147,6 +151,7 @@ typedef struct {
     int32_t small_grid_per_cu;
     int32_t task_grid_per_cu;
     int64_t stage_max_bytes;
+    int32_t dense_min_wedges;
 } sline_tuning;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`

@@ -25,6 +25,7 @@ SPACE: dict[str, list[int]] = {
     "light_len": [2, 4, 8, 16],
     "small_grid_per_cu": [4, 8, 16, 32],
     "task_grid_per_cu": [2, 3, 4],
+    "dense_min_wedges": [0, 1024, 4096, 16384],
 }
 
 

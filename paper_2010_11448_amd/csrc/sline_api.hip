@@ -780,7 +780,9 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS, L.start,
                                     L.cost),
               "lookup members");
-    hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, L.ntask), "task count");
+    hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, ptrI, IS.item_end, IS.full ? 1 : 0,
+                                   L.ntask),
+              "task count");
     hip_check(c, launch_scan_i32_to_i64(st, L.ntask, N, L.tbase, L.part64), "task scan");
     int64_t *h = c->host;
     hip_check(c, hipMemcpyAsync(h + 0, L.tbase + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read tasks");
@@ -800,7 +802,8 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     Arena TA;
     TA.base = reinterpret_cast<char *>(c->ws2);
     const TaskLayout TL = plan_tasks(TA, T);
-    hip_check(c, launch_task_fill(st, L.cost, (int32_t)N, tu, L.tbase, TL.item, TL.part, TL.small,
+    hip_check(c, launch_task_fill(st, L.cost, (int32_t)N, tu, ptrI, IS.item_end, IS.full ? 1 : 0,
+                                  L.tbase, TL.item, TL.part, TL.small,
                                   TL.small_item, TL.big, L.tcounts),
               "task fill");
     mark(c, 2);
@@ -1583,6 +1586,7 @@ sline_status sline_get_tuning(sline_ctx *c, sline_tuning *t) {
     t->small_grid_per_cu = c->tune.small_grid_per_cu;
     t->task_grid_per_cu = c->tune.task_grid_per_cu;
     t->stage_max_bytes = c->tune.stage_max_bytes;
+    t->dense_min_wedges = c->tune.dense_min_wedges;
     return SLINE_OK;
 }
 
@@ -1592,7 +1596,7 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     if (!in(t->small_max_wedges, 0, kSmallSlots / 2) || !in(t->task_wedges, 64, 1 << 20) ||
         !in(t->group_parts, 1, 1024) || !in(t->light_len, 0, 64) ||
         !in(t->small_grid_per_cu, 1, 64) || !in(t->task_grid_per_cu, 1, 16) ||
-        t->stage_max_bytes < 0) {
+        t->stage_max_bytes < 0 || !in(t->dense_min_wedges, 0, 1 << 24)) {
         c->last_error = "tuning value out of range";
         return SLINE_EINVAL;
     }
@@ -1604,6 +1608,7 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     c->tune.small_grid_per_cu = t->small_grid_per_cu;
     c->tune.task_grid_per_cu = t->task_grid_per_cu;
     c->tune.stage_max_bytes = t->stage_max_bytes;
+    c->tune.dense_min_wedges = t->dense_min_wedges;
     return SLINE_OK;
 }
 

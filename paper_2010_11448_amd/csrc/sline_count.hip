@@ -99,11 +99,20 @@ struct Range {
     int32_t hi;      // one past the last candidate id
     uint32_t span;   // hi - lo
     uint32_t mul;    // hashed: home bucket = mulhi(j - lo, mul); 0 = dense
-    int32_t limit;   // slots in use (home slots + pad when hashed; a multiple of 4)
+    int32_t limit;   // words in use (home slots + pad when hashed; a multiple of 4)
     int32_t cb;      // hashed: count bits of a slot word
     uint32_t cmask;  // (1 << cb) - 1
+    uint32_t psh;    // dense: 2^psh counters per word (4 x 8, 2 x 16 or 1 x 32 bits)
 };
 
+// Counters per table word, as a shift, for overlaps of up to 2^cb - 1: four
+// 8-bit counters when the item has at most 255 members, two 16-bit ones up
+// to 65535, else one.
+__device__ __forceinline__ uint32_t pack_shift(int32_t cb) { return cb <= 8 ? 2u : cb <= 16 ? 1u : 0u; }
+
+// Dense ranges (span <= slots << pack_shift(cb)) count candidate j in
+// counter j - lo directly: candidate order is counter order, no hashing and
+// no overflow (an overlap never exceeds the item's size).  Wider ranges hash.
 __device__ __forceinline__ Range make_range(int32_t lo, int32_t hi, int32_t slots, int32_t pad,
                                             int32_t cb) {
     Range r;
@@ -113,10 +122,12 @@ __device__ __forceinline__ Range make_range(int32_t lo, int32_t hi, int32_t slot
     r.span = (uint32_t)span;
     r.cb = cb;
     r.cmask = (1u << cb) - 1u;
-    if (span <= slots) {
+    r.psh = pack_shift(cb);
+    if (span <= ((int64_t)slots << r.psh)) {
         r.mul = 0;
-        r.limit = (int32_t)span;
+        r.limit = (int32_t)((span + (1 << r.psh) - 1) >> r.psh);
     } else {
+        r.psh = 0;
         r.mul = (uint32_t)(((uint64_t)(slots >> 2) << 32) / (uint64_t)span);
         r.limit = slots + pad;
     }
@@ -204,8 +215,10 @@ __device__ __forceinline__ bool tab_add4(uint32_t *tab, uint32_t *spare, const R
         in[i] = j[i] < R.hi && x[i] < R.span;
     }
     if (R.mul == 0) {
+        const uint32_t pm = (1u << R.psh) - 1u, bsh = 5u - R.psh;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) atomicAdd(in[i] ? &tab[x[i]] : dummy, 1u);
+        for (int i = 0; i < 4; ++i)
+            atomicAdd(in[i] ? &tab[x[i] >> R.psh] : dummy, 1u << ((x[i] & pm) << bsh));
         return true;
     }
     const uint32_t hmask = ~R.cmask;
@@ -286,9 +299,10 @@ __device__ __forceinline__ void tab_look4(uint32_t *tab, const Range &R, int32_t
         in[i] = j[i] < R.hi && x[i] < R.span;
     }
     if (R.mul == 0) {
+        const uint32_t pm = (1u << R.psh) - 1u, bsh = 5u - R.psh;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (in[i]) atomicAdd(&tab[x[i]], 1u);
+            if (in[i]) atomicAdd(&tab[x[i] >> R.psh], 1u << ((x[i] & pm) << bsh));
         return;
     }
     const uint4 *t4 = reinterpret_cast<const uint4 *>(tab);
@@ -422,7 +436,8 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
     // members past the register window: locate the range by binary search
     for (int32_t k = k0 + (int32_t)threadIdx.x + kR * NT; k < k1; k += NT) {
         const int32_t st = A.start[k];
-        if ((st < 0) != look) continue;
+        // dense ranges count every member in one pass (lookup-only ones too)
+        if (R.mul != 0 && (st < 0) != look) continue;
         const int32_t v = A.memI[k];
         const int32_t e0 = A.ptrS[v + 1];
         const int32_t b = lower_bound(A.itmS, st & kStartMask, e0, R.lo);
@@ -530,6 +545,36 @@ __device__ __forceinline__ uint32_t slot_count(uint32_t w, const Range &R) {
     return R.mul ? (w & R.cmask) : w;
 }
 
+// Counters >= s of one word of a packed dense range (2^psh counters of
+// 32 >> psh bits each).
+__device__ __forceinline__ int32_t packed_hits(uint32_t w, uint32_t psh, uint32_t s) {
+    if (psh == 2u)
+        return ((w & 0xffu) >= s) + (((w >> 8) & 0xffu) >= s) + (((w >> 16) & 0xffu) >= s) +
+               ((w >> 24) >= s);
+    return ((w & 0xffffu) >= s) + ((w >> 16) >= s);
+}
+
+// Pairs (counters >= s) in the bucket of four words q.
+__device__ __forceinline__ int32_t bucket_pairs(const uint4 &q, const Range &R, uint32_t s) {
+    if (R.psh == 0u)
+        return (slot_count(q.x, R) >= s) + (slot_count(q.y, R) >= s) + (slot_count(q.z, R) >= s) +
+               (slot_count(q.w, R) >= s);
+    return packed_hits(q.x, R.psh, s) + packed_hits(q.y, R.psh, s) + packed_hits(q.z, R.psh, s) +
+           packed_hits(q.w, R.psh, s);
+}
+
+// Sum over the wave of n (0 <= n < 32) and the sum over the lanes below this
+// one, from the ballots of its bits (nb = bits of n that can be set).
+__device__ __forceinline__ void wave_bits_prefix(int32_t n, int nb, int32_t &before, int32_t &step) {
+    before = 0;
+    step = 0;
+    for (int b = 0; b < nb; ++b) {
+        const uint64_t m = __ballot((n >> b) & 1);
+        before += (int32_t)lanes_below(m) << b;
+        step += (int32_t)__popcll(m) << b;
+    }
+}
+
 __device__ __forceinline__ void cswap(uint32_t &x, uint32_t &y) {
     const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
     x = lo;
@@ -565,14 +610,16 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
     const uint4 *t4 = reinterpret_cast<const uint4 *>(S.tab);
     uint16_t *const lst = reinterpret_cast<uint16_t *>(S.runs) + wid * LCAP;
     __syncthreads();  // the insertion has finished reading the run arrays
+    // bits of a bucket's pair count: up to 4 pairs, or 16 with packed counters
+    const int nbits = R.psh ? 5 : 3;
     int32_t mine = 0, nact = 0;
     for (int32_t i = b0; i < b1; i += kWave) {
         const int32_t bk = i + lane;
         const uint4 q = bk < b1 ? t4[bk] : make_uint4(0u, 0u, 0u, 0u);
-        const int32_t n = (slot_count(q.x, R) >= s) + (slot_count(q.y, R) >= s) +
-                          (slot_count(q.z, R) >= s) + (slot_count(q.w, R) >= s);
-        mine += __popcll(__ballot(n & 1)) + 2 * __popcll(__ballot(n & 2)) +
-                4 * __popcll(__ballot(n & 4));
+        const int32_t n = bucket_pairs(q, R, s);
+        int32_t nb_before, nb_step;
+        wave_bits_prefix(n, nbits, nb_before, nb_step);
+        mine += nb_step;
         const uint64_t am = __ballot(n > 0);
         const int32_t slot = nact + (int32_t)lanes_below(am);
         if (n > 0 && slot < LCAP) lst[slot] = (uint16_t)bk;
@@ -670,12 +717,28 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
                 ok[k] = c[k] >= s;
                 n += ok[k];
             }
+            if (R.psh) n = bucket_pairs(q, R, s);
             // exclusive prefix of n over the lanes
-            const uint64_t m0 = __ballot(n & 1), m1 = __ballot(n & 2), m2 = __ballot(n & 4);
-            const int32_t before = (int32_t)lanes_below(m0) + 2 * (int32_t)lanes_below(m1) +
-                                   4 * (int32_t)lanes_below(m2);
-            const int32_t step = __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
-            if (R.mul == 0) {
+            int32_t before, step;
+            wave_bits_prefix(n, nbits, before, step);
+            if (R.mul == 0 && R.psh) {
+                // packed dense: counter order is candidate order
+                const uint32_t per = 1u << R.psh, cbits = 32u >> R.psh;
+                const uint32_t cm = (cbits == 32u) ? 0xffffffffu : ((1u << cbits) - 1u);
+                int32_t pos = run + before;
+                for (int k = 0; k < 4 && n; ++k) {
+                    for (uint32_t j = 0; j < per; ++j) {
+                        const uint32_t cnt = (wv[k] >> (j * cbits)) & cm;
+                        if (cnt >= s) {
+                            const int32_t b = R.lo + (int32_t)(((uint32_t)(4 * bk + k) << R.psh) + j);
+                            if (dst_a) dst_a[base + pos] = a - shift;
+                            dst_b[base + pos] = b - shift;
+                            if (dst_w) dst_w[base + pos] = (int32_t)cnt;
+                            ++pos;
+                        }
+                    }
+                }
+            } else if (R.mul == 0) {
                 // dense: slot order is candidate order
                 int32_t pos = run + before;
 #pragma unroll
@@ -812,15 +875,18 @@ __device__ __forceinline__ int64_t run_range(const CountArgs &A, const Smem &S, 
         bool split = too_wide(R);
         if (!split) {
             int32_t nc[kR];
-            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, false, nend, nc);
+            // a dense range has room for every candidate: all members count in
+            // one pass, lookup-only ones included
+            const uint32_t lm = R.mul ? lookm : 0u;
+            insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lm, false, nend, nc);
             ++passes;
             split = S.misc[kMiscOverflow] != 0;
-            if (!split && sa > 1) {
+            if (!split && sa > 1 && R.mul != 0) {
                 // members marked lookup-only count candidates the others inserted
                 __syncthreads();
                 if (threadIdx.x == 0) S.misc[kMiscRuns] = 0;
                 __syncthreads();
-                insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lookm, true, nend, nc);
+                insert_range<NT, RUNCAP>(A, S, R, k0, k1, cur, end, lm, true, nend, nc);
             }
             if (!split) {
                 produced += tab_extract<NT, RUNCAP>(A, S, R, a, sa, t, produced);
@@ -874,11 +940,33 @@ __device__ __forceinline__ int32_t count_bits(int32_t size) {
     return 32 - __clz((uint32_t)max(size, 1));
 }
 
-// Number of tasks of an item and the sub-range of task p.
-__device__ __forceinline__ int32_t task_parts(int64_t cost, int32_t small_max, int32_t target) {
+// Number of tasks of an item: P = ceil(cost / target) equal sub-ranges of
+// its candidate range of `span` ids, each about `target` wedges.  When the
+// item's candidates are dense enough -- at least dense_min wedges (by the
+// planning cost) on average in each sub-range narrow enough for its packed
+// dense counters (slots << pack_shift(size)) -- the item is cut into that many
+// sub-ranges instead (if more): counting one of them costs an add per wedge
+// and an in-order scan, with no hashing.  dense_min = 0 keeps P as is.
+__device__ __forceinline__ int32_t task_parts(int64_t cost, int32_t small_max, int32_t target,
+                                              int64_t span, int32_t size, int32_t dense_min,
+                                              int32_t slots) {
     if (cost <= 0) return 0;
     if (cost <= small_max) return 1;
-    return (int32_t)((cost + target - 1) / target);
+    int64_t P = (cost + target - 1) / target;
+    if (dense_min > 0 && span > 0) {
+        const int64_t cap = (int64_t)slots << pack_shift(32 - __clz((uint32_t)max(size, 1)));
+        const int64_t Pd = (span + cap - 1) / cap;
+        if (Pd > P && cost >= (int64_t)dense_min * Pd) P = Pd;
+    }
+    return (int32_t)min(P, (int64_t)INT32_MAX);
+}
+
+// Candidate span of item a: [a + 1, end) (product mode: [0, end)), end = its
+// graph's end (batches) or N.
+__device__ __forceinline__ int64_t item_span(const int32_t *item_end, int32_t N, int32_t full,
+                                             int32_t a) {
+    const int64_t e = item_end ? item_end[a] : N;
+    return e - (full ? 0 : (int64_t)a + 1);
 }
 
 // Sub-range p of P of the candidate range [first, N) of an item.
@@ -970,7 +1058,10 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t t0 = A.big_tasks[r];
         const int32_t a = A.task_item[t0];
         const int32_t p0 = A.task_part[t0];
-        const int32_t P = task_parts(A.cost[a], A.tune.small_max_wedges, A.tune.task_wedges);
+        const int32_t P = task_parts(A.cost[a], A.tune.small_max_wedges, A.tune.task_wedges,
+                                     item_span(A.item_end, A.N, A.full, a),
+                                     A.ptrI[a + 1] - A.ptrI[a], A.tune.dense_min_wedges,
+                                     kTaskSlots);
         const int32_t p1 = min(P, p0 + A.tune.group_parts);
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
@@ -1031,11 +1122,25 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
 
 // ----------------------------------------------------------- task lists
 
+// What task_parts needs to know about the items besides their cost.
+struct PlanItems {
+    const int32_t *ptrI;      // item lists (sizes)
+    const int32_t *item_end;  // per item: end of its graph's items (batches), or null
+    int32_t full;             // product mode
+    int32_t dense_min;        // Tuning::dense_min_wedges
+};
+
+__device__ __forceinline__ int32_t plan_parts(const PlanItems &I, const int64_t *cost, int32_t N,
+                                              int32_t small_max, int32_t target, int32_t a) {
+    return task_parts(cost[a], small_max, target, item_span(I.item_end, N, I.full, a),
+                      I.ptrI[a + 1] - I.ptrI[a], I.dense_min, kTaskSlots);
+}
+
 __global__ void k_task_count(const int64_t *cost, int32_t N, int32_t small_max, int32_t target,
-                             int32_t *ntask) {
+                             PlanItems I, int32_t *ntask) {
     for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < N;
          a += (int64_t)gridDim.x * blockDim.x)
-        ntask[a] = task_parts(cost[a], small_max, target);
+        ntask[a] = plan_parts(I, cost, N, small_max, target, (int32_t)a);
 }
 
 // counts[0] small tasks, counts[1] task groups
@@ -1045,6 +1150,7 @@ __global__ void k_task_count(const int64_t *cost, int32_t N, int32_t small_max, 
 // with LDS atomics, one per wave and step.
 __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t N,
                                                    int32_t small_max, int32_t target,
+                                                   PlanItems I,
                                                    int32_t group, const int64_t *tbase,
                                                    int32_t *task_item, int32_t *task_part,
                                                    int32_t *small_tasks, int32_t *small_items,
@@ -1060,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
     int32_t ns = 0, ng = 0;
     for (int64_t a = lo + threadIdx.x; a < hi; a += blockDim.x) {
         const int64_t c = cost[a];
-        const int32_t P = task_parts(c, small_max, target);
+        const int32_t P = plan_parts(I, cost, N, small_max, target, (int32_t)a);
         if (P == 0) continue;
         if (c <= small_max) ++ns;
         else ng += (P + group - 1) / group;
@@ -1085,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
         int64_t t0 = 0;
         if (a < hi) {
             c = cost[a];
-            P = task_parts(c, small_max, target);
+            P = plan_parts(I, cost, N, small_max, target, (int32_t)a);
             if (P > 0) t0 = tbase[a];
         }
         for (int32_t p = 0; p < P; ++p) {
@@ -1176,14 +1282,17 @@ inline int grid_for(int64_t work, int per_block, int cap) {
 }  // namespace
 
 hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                              int32_t *ntask) {
     if (N <= 0) return hipSuccess;
+    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges};
     k_task_count<<<grid_for(N, 256, 65536), 256, 0, st>>>(cost, N, tu.small_max_wedges,
-                                                         tu.task_wedges, ntask);
+                                                         tu.task_wedges, I, ntask);
     return hipGetLastError();
 }
 
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                            const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
                             int32_t *counts) {
@@ -1191,7 +1300,8 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
     const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
     const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
     const int64_t grid = ((int64_t)N + chunk - 1) / chunk;
-    k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges,
+    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges};
+    k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges, I,
                                                 std::max(1, tu.group_parts), tbase, task_item,
                                                 task_part, small_tasks, small_items, big_tasks,
                                                 counts, chunk);

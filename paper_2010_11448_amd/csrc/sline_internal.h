@@ -28,6 +28,7 @@ struct Tuning {
     int32_t small_grid_per_cu = 16;  // one-wave workgroups per CU for the small kernel
     int32_t task_grid_per_cu = 4;    // resident workgroups per CU for the task kernel
     int64_t stage_max_bytes = 96ll << 30;  // cap of the staging pool (one counting pass)
+    int32_t dense_min_wedges = 4096;  // cut items into dense sub-ranges when each gets this many wedges
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -125,10 +126,12 @@ hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t
 // in big_tasks; counts[0] / [1]
 // receive the list lengths.
 hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                              int32_t *ntask);
 // big_tasks receives, per group of up to group_parts consecutive tasks of an
 // item, the index of the group's first task; counts[1] = number of groups.
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
+                            const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
                             int32_t *counts);

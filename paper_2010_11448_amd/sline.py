@@ -59,7 +59,7 @@ class sline_tuning(ctypes.Structure):
     _fields_ = [("small_max_wedges", ctypes.c_int32), ("task_wedges", ctypes.c_int32),
                 ("group_parts", ctypes.c_int32), ("light_len", ctypes.c_int32),
                 ("small_grid_per_cu", ctypes.c_int32), ("task_grid_per_cu", ctypes.c_int32),
-                ("stage_max_bytes", ctypes.c_int64)]
+                ("stage_max_bytes", ctypes.c_int64), ("dense_min_wedges", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
