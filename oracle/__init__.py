@@ -13,7 +13,20 @@ transpose):
 * ``wedge(...)``  -- O3, the alternative algorithm of Sec. IV-B with the
   visited array turned into an exact counter and degree-based pruning
   (Sec. IV-C); exact, validated against O1.
+* ``alg_h(...)``  -- O2, the efficient algorithm with heuristics (Sec. IV-C)
+  as printed, each heuristic a switch: the variants f0..f4 of Table III.
 * ``transpose(...)`` -- the dual's item lists.
+
+The pipeline stages after L_s (Table I), on an oracle edge list:
+
+* ``filter_s(L, s)`` -- L_s from a weighted L_s' with s' <= s (Sec. III:
+  L_s keeps the pairs of L_1 with w >= s, with the same w).
+* ``squeeze(L, n_items)`` -- ID squeezing (Sec. IV-E): contiguous new ids for
+  the items that occur in L, in the order of their original ids.
+* ``adjacency(...)`` -- the line graph's adjacency as a symmetric CSR over
+  the squeezed ids (Sec. IV-E: materializing it after squeezing).
+* ``components(n_items, L)`` -- the s-connected components (Table I).
+* ``relabel(...)`` -- relabel-by-degree (Sec. IV-F) and ``map_back``.
 
 Each returns ``Pairs(a, b, w)`` (int32 numpy arrays, sorted by (a, b), a < b,
 w >= s) and/or ``Stats`` (pair count, weight sum, order-independent digest,
@@ -73,6 +86,10 @@ def _load():
         lib.oracle_wedge_rows.argtypes = [i32p, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                                           i32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                           P(_Pairs), P(_Stats)]
+        lib.oracle_alg_h_rows.argtypes = [i32p, i32p, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, i32p, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int, P(_Pairs), P(_Stats)]
+        lib.oracle_components.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int64, i32p]
         lib.oracle_free_pairs.argtypes = [P(_Pairs)]
         lib.oracle_mix.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         lib.oracle_mix.restype = ctypes.c_uint64
@@ -215,3 +232,116 @@ def wedge(row_ptr, col, n_edges: int, n_vertices: int, s: int, dual: int = 0,
 def mix(a: int, b: int, w: int) -> int:
     """The digest term the oracle sums for one output triple."""
     return int(_load().oracle_mix(a, b, w))
+
+
+# Heuristics of O2 (Sec. IV-C) and the variants of Table III.
+H_PRUNE, H_VISITED, H_SHORT = 1, 2, 4
+VARIANTS = {"f0": H_PRUNE | H_VISITED | H_SHORT, "f1": H_PRUNE, "f2": H_VISITED, "f3": H_SHORT,
+            "f4": 0}
+
+
+def alg_h(row_ptr, col, n_edges: int, n_vertices: int, s: int, dual: int = 0,
+          variant: int = VARIANTS["f0"], rows=None, threads: int = 1, keep: bool = True):
+    """O2: the heuristic algorithm with the given heuristics on; ``Stats``
+    counts its set intersections."""
+    rp, cl, N, rpT, colT = _items(row_ptr, col, n_edges, n_vertices, dual)
+    r, nr = _rows_arg(rows)
+    pairs, st = _Pairs(), _Stats()
+    rc = _load().oracle_alg_h_rows(_ptr(rp), _ptr(cl), _ptr(rpT), _ptr(colT), N, s, int(variant),
+                                   _ptr(r), nr, threads, int(keep), ctypes.byref(pairs),
+                                   ctypes.byref(st))
+    return _finish(rc, pairs, st, keep)
+
+
+def filter_s(L: Pairs, s: int) -> Pairs:
+    """The pairs of a weighted L_s' (s' <= s) with w >= s: L_s (Sec. III)."""
+    keep = np.asarray(L.w) >= s
+    return Pairs(np.asarray(L.a)[keep], np.asarray(L.b)[keep], np.asarray(L.w)[keep])
+
+
+def squeeze(L: Pairs, n_items: int):
+    """ID squeezing (Sec. IV-E).  Returns ``(old_id, Pairs)``: old_id[k] is the
+    original id of new id k -- the items occurring in L, ascending -- and the
+    pairs are L with both ids replaced by the new ones (still sorted, a < b)."""
+    a = np.asarray(L.a, dtype=np.int64)
+    b = np.asarray(L.b, dtype=np.int64)
+    present = np.zeros(n_items, dtype=bool)
+    present[a] = True
+    present[b] = True
+    old_id = np.flatnonzero(present).astype(np.int32)
+    new_of_old = np.full(n_items, -1, dtype=np.int64)
+    new_of_old[old_id] = np.arange(len(old_id))
+    return old_id, Pairs(new_of_old[a].astype(np.int32), new_of_old[b].astype(np.int32),
+                         np.asarray(L.w, dtype=np.int32).copy())
+
+
+def adjacency(L: Pairs, n_nodes: int):
+    """The adjacency of the undirected graph L over nodes 0..n_nodes-1 as a
+    CSR: ``(row_ptr (int64, n_nodes + 1), col, w)``, every edge {a, b} in row
+    a and in row b, each row in ascending neighbour order."""
+    a = np.asarray(L.a, dtype=np.int64)
+    b = np.asarray(L.b, dtype=np.int64)
+    w = np.asarray(L.w, dtype=np.int32)
+    rows = np.concatenate([a, b])
+    cols = np.concatenate([b, a])
+    ws = np.concatenate([w, w])
+    order = np.lexsort((cols, rows))
+    row_ptr = np.zeros(n_nodes + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n_nodes), out=row_ptr[1:])
+    return row_ptr, cols[order].astype(np.int32), ws[order]
+
+
+def components(n_items: int, L: Pairs) -> np.ndarray:
+    """s-connected components (Table I) of the graph L on items 0..n-1:
+    comp[x] = the smallest item of x's component (an item with no pair is a
+    component of its own)."""
+    a = _i32(L.a)
+    b = _i32(L.b)
+    comp = np.zeros(max(n_items, 1), dtype=np.int32)
+    rc = _load().oracle_components(n_items, _ptr(a) if len(a) else None,
+                                   _ptr(b) if len(b) else None, len(a), _ptr(comp))
+    if rc != 0:
+        raise ValueError(f"oracle_components failed ({rc})")
+    return comp[:n_items]
+
+
+def relabel(row_ptr, col, n_edges: int, n_vertices: int, dual: int = 0,
+            descending: bool = True):
+    """Relabel-by-degree (Sec. IV-F) of the items of one side: new id k goes to
+    the item of the k-th largest size (``descending``) or smallest, ties by
+    original id.  Returns ``(perm, row_ptr', col', n_edges', n_vertices')``:
+    perm[k] = original id of new item k, and the CSR of the same hypergraph
+    with the items renumbered (rows reordered for the primal side; member ids
+    of the vertex side rewritten, rows re-sorted, for the dual)."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    cl = np.asarray(col, dtype=np.int64)
+    if dual:
+        size = np.bincount(cl, minlength=n_vertices)
+    else:
+        size = np.diff(rp)
+    key = -size if descending else size
+    perm = np.lexsort((np.arange(len(size)), key)).astype(np.int32)  # size order, then id
+    if dual:
+        new_of_old = np.empty(len(size), dtype=np.int64)
+        new_of_old[perm] = np.arange(len(size))
+        row = np.repeat(np.arange(n_edges), np.diff(rp))
+        newc = new_of_old[cl]
+        order = np.lexsort((newc, row))
+        return perm, rp.astype(np.int32), newc[order].astype(np.int32), n_edges, n_vertices
+    lens = np.diff(rp)[perm]
+    nrp = np.zeros(n_edges + 1, dtype=np.int64)
+    np.cumsum(lens, out=nrp[1:])
+    ncol = np.concatenate([cl[rp[i]:rp[i + 1]] for i in perm]) if n_edges else cl[:0]
+    return perm, nrp.astype(np.int32), ncol.astype(np.int32), n_edges, n_vertices
+
+
+def map_back(L: Pairs, perm) -> Pairs:
+    """Pairs of relabeled items in original ids: (perm[a], perm[b]) ordered so
+    the smaller id comes first, then sorted by (a, b)."""
+    perm = np.asarray(perm, dtype=np.int64)
+    x = perm[np.asarray(L.a, dtype=np.int64)]
+    y = perm[np.asarray(L.b, dtype=np.int64)]
+    a, b = np.minimum(x, y), np.maximum(x, y)
+    order = np.lexsort((b, a))
+    return Pairs(a[order].astype(np.int32), b[order].astype(np.int32),
+                 np.asarray(L.w, dtype=np.int32)[order])

@@ -30,6 +30,22 @@
  *      Sec. IV-C), which cannot change the result since w_ab <= min(|S_a|,
  *      |S_b|).  It is exact (not an approximation) and is checked against O1.
  *
+ *  O2  oracle_alg_h_rows -- the efficient algorithm with heuristics of
+ *      Sec. IV-C (the second printed algorithm) with each heuristic as a
+ *      switch, so that the variants f0..f4 of Sec. V-C (Table III) run as
+ *      printed: degree-based pruning of e_i and e_j (size < s), skipping
+ *      hyperedges already visited for e_i, and a set intersection that stops
+ *      once s common members are found (short-circuit).  The strictly upper
+ *      triangle is kept in every variant, as Sec. V-C states.  L_s is a set,
+ *      so a pair met again through another shared vertex (visited skipping
+ *      off) is added once.  Output weights are exact: when the intersection
+ *      stopped early, an accepted pair's overlap is counted in full.  The
+ *      stats count the set intersections made (Table I's measure of work).
+ *
+ *  oracle_components -- the connected components of the graph L_s (the
+ *      s-connected components of Table I): union-find over the edge list,
+ *      every component labelled by its smallest item id.
+ *
  * Parallelism: items are dealt cyclically to threads (Sec. IV-F, cyclic
  * range); each thread keeps its own row buffers and the rows are concatenated
  * in item order at the end, so the result does not depend on the thread count.
@@ -54,8 +70,8 @@ typedef struct {
     int64_t n_pairs;        /* |L_s| over the rows visited              */
     int64_t sum_w;          /* sum of w over those pairs                 */
     uint64_t digest;        /* sum over pairs of mix(a, b, w), mod 2^64  */
-    int64_t wedges;         /* O3: increments made;  O1: 0               */
-    int64_t intersections;  /* O1: merges made;      O3: 0               */
+    int64_t wedges;         /* O3: increments made;  O1, O2: 0           */
+    int64_t intersections;  /* O1, O2: set intersections made; O3: 0     */
 } oracle_stats;
 
 /* ------------------------------------------------------------ utilities */
@@ -131,8 +147,9 @@ static int rb_push(rowbuf *r, int32_t b, int32_t w) {
 
 typedef struct {
     const int32_t *rp, *col;   /* item lists */
-    const int32_t *rpT, *colT; /* membership lists (O3 only) */
+    const int32_t *rpT, *colT; /* membership lists (O2, O3) */
     int32_t N, s, skip_small, keep;
+    int32_t variant;           /* O2: heuristics on (ORACLE_H_* bits) */
     const int32_t *rows;       /* rows to visit, NULL = all */
     int64_t nrows;
     int tid, nthreads;
@@ -206,11 +223,92 @@ static void *wedge_worker(void *p) {
     return NULL;
 }
 
+/* O2 heuristic switches (Sec. IV-C). */
+enum { ORACLE_H_PRUNE = 1, ORACLE_H_VISITED = 2, ORACLE_H_SHORT = 4 };
+
+/* At least s common members?  The merge stops as soon as s are found. */
+static int merge_at_least(const int32_t *x, int32_t nx, const int32_t *y, int32_t ny, int32_t s) {
+    int32_t i = 0, j = 0, c = 0;
+    while (i < nx && j < ny) {
+        if (x[i] < y[j]) ++i;
+        else if (y[j] < x[i]) ++j;
+        else {
+            if (++c >= s) return 1;
+            ++i;
+            ++j;
+        }
+    }
+    return 0;
+}
+
+static void *alg_h_worker(void *p) {
+    job *J = (job *)p;
+    const int prune = J->variant & ORACLE_H_PRUNE;
+    const int visit = J->variant & ORACLE_H_VISITED;
+    const int shortc = J->variant & ORACLE_H_SHORT;
+    uint8_t *visited = (uint8_t *)calloc((size_t)J->N + 1, 1);
+    int64_t cap = 1024;
+    int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);  /* accepted j of e_i */
+    int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * ((size_t)J->N + 1));
+    if (!visited || !acc || !touched) {
+        J->err = -2;
+        free(visited); free(acc); free(touched);
+        return NULL;
+    }
+    for (int64_t ri = J->tid; ri < J->nrows && !J->err; ri += J->nthreads) {
+        const int32_t i = J->rows ? J->rows[ri] : (int32_t)ri;
+        const int32_t *Si = J->col + J->rp[i];
+        const int32_t ni = J->rp[i + 1] - J->rp[i];
+        if (prune && ni < J->s) continue;              /* degree-based pruning of e_i */
+        int64_t nt = 0, na = 0;
+        for (int32_t k = J->rp[i]; k < J->rp[i + 1]; ++k) {
+            const int32_t v = J->col[k];
+            for (int32_t t = J->rpT[v]; t < J->rpT[v + 1]; ++t) {
+                const int32_t j = J->colT[t];
+                if (i >= j) continue;                  /* strictly upper triangle */
+                const int32_t *Sj = J->col + J->rp[j];
+                const int32_t nj = J->rp[j + 1] - J->rp[j];
+                if (prune && nj < J->s) continue;      /* degree-based pruning of e_j */
+                if (visit) {                           /* skip hyperedges already visited */
+                    if (visited[j]) continue;
+                    visited[j] = 1;
+                    touched[nt++] = j;
+                }
+                J->st.intersections++;
+                const int ok = shortc ? merge_at_least(Si, ni, Sj, nj, J->s)
+                                      : merge_count(Si, ni, Sj, nj) >= J->s;
+                if (ok) {
+                    if (na == cap) {
+                        int32_t *g = (int32_t *)realloc(acc, sizeof(int32_t) * (size_t)(2 * cap));
+                        if (!g) { J->err = -2; break; }
+                        acc = g;
+                        cap *= 2;
+                    }
+                    acc[na++] = j;
+                }
+            }
+            if (J->err) break;
+        }
+        for (int64_t t = 0; t < nt; ++t) visited[touched[t]] = 0;
+        /* L_s is a set: each accepted e_j once, in id order, with its overlap */
+        qsort(acc, (size_t)na, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < na && !J->err; ++t) {
+            if (t > 0 && acc[t] == acc[t - 1]) continue;
+            const int32_t j = acc[t];
+            record(J, ri, i, j, merge_count(Si, ni, J->col + J->rp[j], J->rp[j + 1] - J->rp[j]));
+        }
+    }
+    free(visited);
+    free(acc);
+    free(touched);
+    return NULL;
+}
+
 /* Run `worker` over the rows with `nthreads` cyclic workers and gather. */
 static int run(void *(*worker)(void *), const int32_t *rp, const int32_t *col,
                const int32_t *rpT, const int32_t *colT, int32_t N, int32_t s,
-               int32_t skip_small, const int32_t *rows, int64_t nrows, int nthreads,
-               int keep, oracle_pairs *out, oracle_stats *stats) {
+               int32_t skip_small, int32_t variant, const int32_t *rows, int64_t nrows,
+               int nthreads, int keep, oracle_pairs *out, oracle_stats *stats) {
     if (N < 0 || s < 1 || (N > 0 && !rp) || nthreads < 1) return -1;
     if (!rows) nrows = N;
     for (int64_t r = 0; rows && r < nrows; ++r)
@@ -222,6 +320,7 @@ static int run(void *(*worker)(void *), const int32_t *rp, const int32_t *col,
     for (int t = 0; t < nthreads; ++t) {
         J[t].rp = rp; J[t].col = col; J[t].rpT = rpT; J[t].colT = colT;
         J[t].N = N; J[t].s = s; J[t].skip_small = skip_small; J[t].keep = keep;
+        J[t].variant = variant;
         J[t].rows = rows; J[t].nrows = nrows; J[t].tid = t; J[t].nthreads = nthreads;
         J[t].row_count = row_count;
     }
@@ -277,7 +376,7 @@ static int run(void *(*worker)(void *), const int32_t *rp, const int32_t *col,
 int oracle_naive_rows(const int32_t *rp, const int32_t *col, int32_t N, int32_t s,
                       int32_t skip_small, const int32_t *rows, int64_t nrows,
                       int nthreads, int keep, oracle_pairs *out, oracle_stats *stats) {
-    return run(naive_worker, rp, col, NULL, NULL, N, s, skip_small, rows, nrows,
+    return run(naive_worker, rp, col, NULL, NULL, N, s, skip_small, 0, rows, nrows,
                nthreads, keep, out, stats);
 }
 
@@ -288,8 +387,45 @@ int oracle_wedge_rows(const int32_t *rp, const int32_t *col, const int32_t *rpT,
                       int64_t nrows, int nthreads, int keep, oracle_pairs *out,
                       oracle_stats *stats) {
     if (!rpT && N > 0) return -1;
-    return run(wedge_worker, rp, col, rpT, colT, N, s, 1, rows, nrows, nthreads, keep,
+    return run(wedge_worker, rp, col, rpT, colT, N, s, 1, 0, rows, nrows, nthreads, keep,
                out, stats);
+}
+
+/* O2.  As O3's arguments, plus `variant`: the ORACLE_H_* heuristics that are
+ * on (7 = f0, PRUNE = f1, VISITED = f2, SHORT = f3, 0 = f4 of Table III). */
+int oracle_alg_h_rows(const int32_t *rp, const int32_t *col, const int32_t *rpT,
+                      const int32_t *colT, int32_t N, int32_t s, int32_t variant,
+                      const int32_t *rows, int64_t nrows, int nthreads, int keep,
+                      oracle_pairs *out, oracle_stats *stats) {
+    if ((!rpT && N > 0) || variant < 0 || variant > 7) return -1;
+    return run(alg_h_worker, rp, col, rpT, colT, N, s, 0, variant, rows, nrows, nthreads, keep,
+               out, stats);
+}
+
+/* Connected components of the graph on items 0..N-1 with edges (a[e], b[e]):
+ * comp[x] = the smallest item of x's component (an item without edges is
+ * its own component).  Union-find with path halving; a union links the
+ * larger root under the smaller, so a component's root is its minimum. */
+static int32_t uf_find(int32_t *parent, int32_t x) {
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+int oracle_components(int32_t N, const int32_t *a, const int32_t *b, int64_t n, int32_t *comp) {
+    if (N < 0 || n < 0 || (N > 0 && !comp) || (n > 0 && (!a || !b))) return -1;
+    for (int32_t x = 0; x < N; ++x) comp[x] = x;
+    for (int64_t e = 0; e < n; ++e) {
+        if (a[e] < 0 || a[e] >= N || b[e] < 0 || b[e] >= N) return -1;
+        int32_t ra = uf_find(comp, a[e]), rb = uf_find(comp, b[e]);
+        if (ra == rb) continue;
+        if (ra < rb) comp[rb] = ra;
+        else comp[ra] = rb;
+    }
+    for (int32_t x = 0; x < N; ++x) comp[x] = uf_find(comp, x);
+    return 0;
 }
 
 void oracle_free_pairs(oracle_pairs *p) {

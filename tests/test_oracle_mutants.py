@@ -20,6 +20,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_pins_stages as stages
 
 SRC = os.path.join(os.path.dirname(os.path.abspath(oracle.__file__)), "sline_oracle.c")
 
@@ -30,7 +31,11 @@ MUTANTS = [
     ("o1 skips the next item",
      "for (int32_t b = a + 1; b < J->N; ++b)", "for (int32_t b = a + 2; b < J->N; ++b)"),
     ("merge advances the wrong list",
-     "if (x[i] < y[j]) ++i;", "if (x[i] < y[j]) ++j;"),
+     "if (x[i] < y[j]) ++i;\n        else if (y[j] < x[i]) ++j;\n        else { ++c;",
+     "if (x[i] < y[j]) ++j;\n        else if (y[j] < x[i]) ++j;\n        else { ++c;"),
+    ("short-circuit merge advances the wrong list",
+     "if (x[i] < y[j]) ++i;\n        else if (y[j] < x[i]) ++j;\n        else {\n",
+     "if (x[i] < y[j]) ++j;\n        else if (y[j] < x[i]) ++j;\n        else {\n"),
     ("o3 counts the item with itself",
      "if (b <= a) continue;", "if (b < a) continue;"),
     ("o3 prunes items of size s",
@@ -47,6 +52,20 @@ MUTANTS = [
      "out->w[o] = Jt->out.w[base + q];", "out->w[o] = Jt->out.b[base + q];"),
     ("weight sum counts pairs",
      "J->st.sum_w += w;", "J->st.sum_w += 1;"),
+    ("o2 prunes items of size s",
+     "if (prune && ni < J->s) continue;", "if (prune && ni <= J->s) continue;"),
+    ("o2 never resets its visited flags",
+     "for (int64_t t = 0; t < nt; ++t) visited[touched[t]] = 0;", ";"),
+    ("o2 short-circuits one member early",
+     "if (++c >= s) return 1;", "if (++c >= s - 1) return 1;"),
+    ("o2 keeps the diagonal",
+     "if (i >= j) continue;                  /* strictly upper triangle */",
+     "if (i > j) continue;"),
+    ("o2 counts an intersection per accepted pair only",
+     "J->st.intersections++;\n                const int ok",
+     "const int ok"),
+    ("components link the smaller root under the larger",
+     "if (ra < rb) comp[rb] = ra;", "if (ra < rb) comp[ra] = rb;"),
 ]
 
 
@@ -71,6 +90,14 @@ BATTERY = [
     ("weight sum closed form", pins.test_weight_sum_closed_form),
     ("naive intersection count", pins.test_naive_makes_all_pairs_intersections),
     ("digest", pins.test_digest_terms_and_sum),
+    ("o2 variants equal the dense product",
+     lambda: [stages.test_o2_variants_return_the_dense_product_result(v)
+              for v in sorted(oracle.VARIANTS)]),
+    ("o2 intersection closed forms",
+     lambda: [stages.test_o2_intersection_counts_match_closed_forms(v)
+              for v in sorted(oracle.VARIANTS)]),
+    ("components match scipy", stages.test_components_match_scipy),
+    ("components closed forms", stages.test_components_closed_forms),
 ]
 
 
@@ -107,6 +134,7 @@ def test_unmodified_copy_passes_every_pin(tmp_path, monkeypatch):
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_planted_mistake_fails_a_pin(name, old, new, tmp_path, monkeypatch):
     text = open(SRC).read()
+    old, new = old.replace("\\n", "\n"), new.replace("\\n", "\n")
     assert text.count(old) == 1, f"mutation site for '{name}' not found once in the oracle"
     lib = _build(text.replace(old, new), tmp_path, "mutant")
     caught = _first_failure(lib, monkeypatch)
