@@ -43,10 +43,34 @@ enum {
                                  checks that guard memory always run)       */
     SLINE_PROFILE = 2u,       /* time the stages with HIP events on the
                                  context's stream (see sline_stats)          */
-    SLINE_NO_WEIGHTS = 4u     /* pairs only: the w array is neither needed nor
+    SLINE_NO_WEIGHTS = 4u,    /* pairs only: the w array is neither needed nor
                                  written (caller buffers may leave w NULL;
                                  library-allocated results have w = NULL).
                                  Saves a third of the output traffic.      */
+    /* Relabel-by-degree (Sec. IV-F): sline_build renumbers the items of the
+     * side built by size, largest first (DESC) or smallest first (ASC), ties
+     * by id, counts on the renumbered hypergraph and maps the result back to
+     * the caller's ids -- same output, different work order.  At most one of
+     * the two; results of 2^31 pairs or more are refused (SLINE_EINVAL). */
+    SLINE_RELABEL_DESC = 8u,
+    SLINE_RELABEL_ASC = 16u,
+    /* Heuristic ablation (Sec. IV-C; the variants f0..f4 of Table III are
+     * f0 = none of these, f1 = NO_VISITED | NO_SHORTCUT, f2 = NO_PRUNE |
+     * NO_SHORTCUT, f3 = NO_PRUNE | NO_VISITED, f4 = all three).  They change
+     * the work, never the result (results of 2^31 pairs or more are refused
+     * with NO_VISITED).
+     *   NO_PRUNE     no degree-based pruning: items smaller than s stay in
+     *                the member lists and are walked (they cannot reach s)
+     *   NO_VISITED   no visited skipping: one set intersection |S_a & S_b|
+     *                (two-pointer merge) per wedge (a, v, b) instead of one
+     *                counter increment; a pair enters once, from its first
+     *                shared member
+     *   NO_SHORTCUT  no short-circuit: with NO_VISITED the intersections run
+     *                to the end instead of stopping at s; otherwise every
+     *                member inserts candidates (no lookup-only members) */
+    SLINE_NO_PRUNE = 32u,
+    SLINE_NO_VISITED = 64u,
+    SLINE_NO_SHORTCUT = 128u
 };
 
 typedef struct sline_ctx sline_ctx;
@@ -122,6 +146,8 @@ typedef struct {
     int64_t product_nnz;  /* entries of the materialized product H H^T          */
     double ms_product;    /* product time (host clock)                          */
     double ms_filter;     /* filter time (host clock)                           */
+    /* SLINE_NO_VISITED builds only                                           */
+    int64_t intersections;/* set intersections made (one per wedge)             */
 } sline_stats;
 
 /* Launch parameters of the counting stage (they change speed, never the
@@ -204,6 +230,66 @@ sline_status sline_build(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
  * caller.  Every call clears what it needs zeroed. */
 sline_status sline_build_noalloc(sline_ctx *ctx, sline_csr H, int32_t s, int32_t dual,
                                  uint32_t flags, sline_edges *out);
+
+/* ------------------------------------------------ after L_s (Table I)
+ * L_s stratifies by s: L_s keeps the pairs of L_1 with w >= s, with the same
+ * weights (Sec. III), so L_s is L_s' (s' <= s) filtered.  These calls take an
+ * edge list on the device as sline_build returns it: n_pairs >= 0, a, b (and
+ * w where stated) device arrays of n_pairs entries. */
+
+/* L_s from a weighted L_s' with s' <= s: the pairs of `in` with w >= s, in
+ * their order.  in->w is required (SLINE_EINVAL if NULL with pairs).  `out`
+ * and the capacity protocol as in sline_build (flags: SLINE_NO_WEIGHTS drops
+ * the output weights); a retry after SLINE_ECAPACITY filters again. */
+sline_status sline_filter(sline_ctx *ctx, const sline_edges *in, int32_t s, uint32_t flags,
+                          sline_edges *out);
+
+/* An s-sweep: L_s for every s of s_list (n_s entries, each >= 1, any order)
+ * of one hypergraph and side.  Only the smallest s is counted (sline_build);
+ * every other L_s is filtered from the next smaller one.  outs[i] receives
+ * L_{s_list[i]}; every outs[i] must have capacity 0 (library-allocated, free
+ * each with sline_edges_free).  flags as in sline_build except
+ * SLINE_NO_WEIGHTS (the filters need the weights).  On failure no output is
+ * left allocated. */
+sline_status sline_build_sweep(sline_ctx *ctx, sline_csr H, int32_t n_s, const int32_t *s_list,
+                               int32_t dual, uint32_t flags, sline_edges *outs);
+
+/* The line graph as a graph (Sec. IV-E).  Nodes are the items that occur in
+ * L, renumbered 0..n_nodes-1 in the order of their ids ("ID squeezing");
+ * old_id maps back.  The adjacency is symmetric: pair (a, b, w) is the arc
+ * (a', b') in row a' and the arc (b', a') in row b'; every row ascending.
+ * All arrays are device memory allocated through the context's allocator;
+ * release them with sline_graph_free. */
+typedef struct {
+    int32_t n_nodes;
+    int64_t n_arcs;    /* 2 * n_pairs                                       */
+    int32_t *old_id;   /* [n_nodes] original id of each node, ascending     */
+    int64_t *row_ptr;  /* [n_nodes + 1]                                     */
+    int32_t *col;      /* [n_arcs] neighbours (squeezed ids)                */
+    int32_t *w;        /* [n_arcs] overlaps, NULL with SLINE_NO_WEIGHTS     */
+} sline_graph;
+
+/* Squeeze L (pairs of items in [0, n_items), sorted by (a, b), a < b) and
+ * build its adjacency (Sec. IV-E).  L->w is required unless flags has
+ * SLINE_NO_WEIGHTS.  SLINE_EINVAL for ids out of range, pairs out of order or
+ * n_pairs >= 2^31; SLINE_ENOMEM, SLINE_EDEVICE as usual.  On failure *G is
+ * left untouched. */
+sline_status sline_squeeze(sline_ctx *ctx, int32_t n_items, const sline_edges *L, uint32_t flags,
+                           sline_graph *G);
+
+/* Release the arrays of a graph from sline_squeeze and zero the struct. */
+sline_status sline_graph_free(sline_ctx *ctx, sline_graph *G);
+
+/* s-connected components (Table I): the connected components of the graph
+ * L on items 0..n_items-1 (L as in sline_squeeze, weights not read).
+ *   comp          device int32[n_items], caller-owned: comp[x] = the
+ *                 smallest item of x's component (an item in no pair is its
+ *                 own component)
+ *   n_components  host, may be NULL: components with at least two items
+ *                 (those of the squeezed graph)
+ * Errors as in sline_squeeze (any n_pairs is accepted). */
+sline_status sline_components(sline_ctx *ctx, int32_t n_items, const sline_edges *L,
+                              int32_t *comp, int64_t *n_components);
 
 /* Companion route to the same result (Sec. IV-D): the product C = H H^T
  * (H* H*^T for dual = 1) with both triangles and the diagonal, computed row

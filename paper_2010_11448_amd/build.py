@@ -7,8 +7,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["sline_prep.hip", "sline_count.hip", "sline_batch.hip", "sline_api.hip",
-           "sline_server.hip"]
+SOURCES = ["sline_prep.hip", "sline_count.hip", "sline_batch.hip", "sline_stages.hip",
+           "sline_api.hip", "sline_server.hip"]
 TARGET = os.path.join(HERE, "libsline.so")
 
 HIPCC_FLAGS = [

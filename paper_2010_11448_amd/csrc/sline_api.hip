@@ -582,6 +582,17 @@ struct ItemS {
 
 sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
                         sline_edges *out, const ItemS &IS);
+sline_status relabel_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual,
+                          uint32_t flags, sline_edges *out);
+sline_status intersect_build(sline_ctx *c, const int32_t *ptrI, const int32_t *memI,
+                             const int32_t *ptrS, const int32_t *itmS, const int32_t *start,
+                             int32_t N, int32_t s, uint32_t flags, int32_t *cnt, int64_t *off,
+                             int64_t *part64, unsigned long long *inters, sline_edges *out,
+                             sline_stats &S);
+
+// Flags that only a plain single-graph build understands.
+constexpr uint32_t kBuildOnlyFlags = SLINE_RELABEL_DESC | SLINE_RELABEL_ASC | SLINE_NO_PRUNE |
+                                     SLINE_NO_VISITED | SLINE_NO_SHORTCUT;
 
 sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
                         sline_edges *out) {
@@ -597,6 +608,11 @@ sline_status build_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         (out->capacity > 0 && (!out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))))) {
         set_err(c, "output buffers: capacity > 0 requires a, b and (without SLINE_NO_WEIGHTS) w");
         return SLINE_EINVAL;
+    }
+    if (flags & (SLINE_RELABEL_DESC | SLINE_RELABEL_ASC)) {
+        c->pending.valid = false;
+        release_pool(c);
+        return relabel_impl(c, H, s, dual, flags, out);
     }
     if (same_call(c->pending, H, s, dual, flags)) {
         const int64_t total = c->pending.total;
@@ -634,6 +650,10 @@ sline_status noalloc_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t d
     if (out->capacity <= 0 || !out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))) {
         set_err(c, "sline_build_noalloc writes into caller buffers only: capacity > 0 and a, b "
                    "and (without SLINE_NO_WEIGHTS) w are required");
+        return SLINE_EINVAL;
+    }
+    if (flags & kBuildOnlyFlags) {
+        set_err(c, "sline_build_noalloc takes neither relabeling nor the ablation flags");
         return SLINE_EINVAL;
     }
     void *base = scratch_address(c->device);
@@ -726,7 +746,8 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         if (out->capacity == 0) out->a = out->b = out->w = nullptr;
         return SLINE_OK;
     }
-    const bool filt = IS.s_max > 1;
+    const bool noprune = (flags & SLINE_NO_PRUNE) != 0;
+    const bool filt = IS.s_max > 1 && !noprune;
     Arena sizing;
     plan_layout(sizing, m, n, nnz, N, M, filt);
     ensure_ws(c, sizing.off + 4096);
@@ -774,12 +795,31 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const Tuning tu = c->tune;
     if (!filt && !IS.full)
         hip_check(c, launch_start_from_map(st, nnz, map, L.start), "back-pointers");
-    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, s, IS.s_item, ptrS, itmS, L.cost, L.start,
+    // degree-based pruning (Sec. IV-C) unless switched off: items smaller
+    // than s get no cost and are never walked from
+    hip_check(c, launch_cost(st, ptrI, memI, (int32_t)N, noprune ? 1 : s,
+                             noprune ? nullptr : IS.s_item, ptrS, itmS, L.cost, L.start,
                              L.totals, IS.full ? 1 : 0, IS.full ? 0 : 1),
               "cost");
-    hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS, L.start,
-                                    L.cost),
-              "lookup members");
+    if (flags & SLINE_NO_VISITED) {
+        // one set intersection per wedge instead of the counter table
+        hip_check(c, launch_fill_i64(st, L.passes, 4, 0), "zero counters");
+        int64_t *h = c->host;
+        hip_check(c, hipMemcpyAsync(h + 1, L.totals, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+                  "read totals");
+        sync(c, "wedge totals");
+        S.n_kept = h[1];
+        S.nnz_kept = h[2];
+        S.wedges = h[3];
+        if (c->profile) S.ms_transpose = span_ms(c, 0, 1);
+        return intersect_build(c, ptrI, memI, ptrS, itmS, L.start, (int32_t)N, s, flags, L.ntask,
+                               L.tbase, L.part64, reinterpret_cast<unsigned long long *>(L.passes),
+                               out, S);
+    }
+    if (!(flags & SLINE_NO_SHORTCUT))
+        hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS,
+                                        L.start, L.cost),
+                  "lookup members");
     hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, ptrI, IS.item_end, IS.full ? 1 : 0,
                                    L.ntask),
               "task count");
@@ -1039,6 +1079,10 @@ sline_status batch_split(sline_ctx *c, int32_t G, sline_edges *outs) {
 
 sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int32_t *s,
                         const int32_t *dual, uint32_t flags, sline_edges *outs) {
+    if (flags & kBuildOnlyFlags) {
+        set_err(c, "relabeling and the ablation flags apply to sline_build only");
+        return SLINE_EINVAL;
+    }
     if (G < 0 || (G > 0 && (!Hs || !s || !dual || !outs))) {
         set_err(c, "invalid batch arguments");
         return SLINE_EINVAL;
@@ -1295,6 +1339,10 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
 // degree pruning or lookup-only members: the product does not know s.
 sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual, uint32_t flags,
                          sline_edges *out) {
+    if (flags & kBuildOnlyFlags) {
+        set_err(c, "relabeling and the ablation flags apply to sline_build only");
+        return SLINE_EINVAL;
+    }
     if (!out) {
         set_err(c, "out is NULL");
         return SLINE_EINVAL;
@@ -1414,6 +1462,667 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
     c->stats.ms_product = std::chrono::duration<double, std::milli>(t1 - t0).count();
     c->stats.ms_filter = std::chrono::duration<double, std::milli>(t2 - t1).count();
     return SLINE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------ stages after L_s, variants
+
+namespace {
+
+constexpr uint32_t kRelabelFlags = SLINE_RELABEL_DESC | SLINE_RELABEL_ASC;
+constexpr uint32_t kVariantFlags = SLINE_NO_PRUNE | SLINE_NO_VISITED | SLINE_NO_SHORTCUT;
+
+// One device block for the temporaries of a call, carved by an Arena and
+// released (after the stream is idle) when the call leaves.
+struct TempBlock {
+    sline_ctx *c;
+    void *p = nullptr;
+    size_t bytes = 0;
+    explicit TempBlock(sline_ctx *cc) : c(cc) {}
+    char *get(size_t n, const char *what) {
+        bytes = n + 4096;
+        p = dev_alloc(c, bytes);
+        if (!p) {
+            set_err(c, "allocation of temporaries failed (%s)", what);
+            throw Fail{SLINE_ENOMEM};
+        }
+        return static_cast<char *>(p);
+    }
+    ~TempBlock() {
+        if (p) {
+            (void)hipStreamSynchronize(c->stream);
+            dev_free(c, p, bytes);
+        }
+    }
+};
+
+// Device arrays of an edge list the library allocated, freed on scope exit
+// unless released.
+struct OwnedEdges {
+    sline_ctx *c;
+    sline_edges e{};
+    explicit OwnedEdges(sline_ctx *cc) : c(cc) {}
+    void alloc(int64_t n, bool weights, const char *what) {
+        const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1);
+        e.n_pairs = n;
+        e.a = (int32_t *)dev_alloc(c, bytes);
+        e.b = e.a ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+        e.w = (e.b && weights) ? (int32_t *)dev_alloc(c, bytes) : nullptr;
+        if (!e.a || !e.b || (weights && !e.w)) {
+            set_err(c, "allocation of %s failed", what);
+            throw Fail{SLINE_ENOMEM};
+        }
+    }
+    sline_edges release() {
+        sline_edges r = e;
+        e = sline_edges{};
+        return r;
+    }
+    ~OwnedEdges() {
+        if (e.a || e.b || e.w) {
+            (void)hipStreamSynchronize(c->stream);
+            const size_t bytes = sizeof(int32_t) * (size_t)std::max<int64_t>(e.n_pairs, 1);
+            dev_free(c, e.a, bytes);
+            dev_free(c, e.b, bytes);
+            dev_free(c, e.w, bytes);
+        }
+    }
+};
+
+// Buffers of one radix-sort transpose over n entries with keys in [0, nk).
+struct SortBufs {
+    int32_t *rsK[2], *rsV[2], *hist, *part32, *ptrT;
+};
+
+SortBufs plan_sort(Arena &A, int64_t n, int64_t nk) {
+    SortBufs B{};
+    B.rsK[0] = A.take<int32_t>(n);
+    B.rsK[1] = A.take<int32_t>(n);
+    B.rsV[0] = A.take<int32_t>(n);
+    B.rsV[1] = A.take<int32_t>(n);
+    B.hist = A.take<int32_t>(16 * transpose_tiles(n) + 1);
+    // partials of the digit scans, and of scans over n or nk entries
+    B.part32 = A.take<int32_t>(
+        scan_partials(std::max<int64_t>({16 * transpose_tiles(n), nk, n}) + 1));
+    B.ptrT = A.take<int32_t>(nk + 1);
+    return B;
+}
+
+// Pairs (a, b, w) into (a, b) order: a stable radix sort by b, then a stable
+// one by a, both through the transpose (ids in [0, nk), n < 2^31).  oa, ob,
+// ow receive the result (ow and w may be null).  Writes a1..k2 scratch.
+void sort_pairs(sline_ctx *c, const int32_t *a, const int32_t *b, const int32_t *w, int64_t n,
+                int32_t nk, int32_t *oa, int32_t *ob, int32_t *ow) {
+    if (n <= 0) return;
+    hipStream_t st = c->stream;
+    auto plan = [&](Arena &A, SortBufs &B, int32_t *&a1, int32_t *&b1, int32_t *&k1,
+                    int32_t *&w1, int32_t *&k2) {
+        B = plan_sort(A, n, nk);
+        a1 = A.take<int32_t>(n);
+        b1 = A.take<int32_t>(n);
+        k1 = A.take<int32_t>(n);
+        w1 = w ? A.take<int32_t>(n) : nullptr;
+        k2 = A.take<int32_t>(n);
+    };
+    SortBufs B;
+    int32_t *a1, *b1, *k1, *w1, *k2;
+    Arena sz;
+    plan(sz, B, a1, b1, k1, w1, k2);
+    TempBlock T(c);
+    Arena A;
+    A.base = T.get(sz.off, "pair sort");
+    plan(A, B, a1, b1, k1, w1, k2);
+    const int last = (transpose_passes(nk) - 1) & 1;
+    // by b: a1 = the a of each pair in b order, its sorted b in rsK[last]
+    hip_check(c, launch_transpose(st, b, n, nk, a, B.rsK, B.rsV, B.hist, B.part32, B.ptrT, a1, k1,
+                                  nullptr),
+              "pair sort (second key)");
+    hip_check(c, launch_copy_i32(st, b1, B.rsK[last], n), "pair sort copy");
+    if (w) hip_check(c, launch_gather(st, w, k1, n, w1), "pair sort gather");
+    // by a, stable: ties keep b order
+    hip_check(c, launch_transpose(st, a1, n, nk, b1, B.rsK, B.rsV, B.hist, B.part32, B.ptrT, ob, k2,
+                                  nullptr),
+              "pair sort (first key)");
+    hip_check(c, launch_copy_i32(st, oa, B.rsK[last], n), "pair sort copy");
+    if (w && ow) hip_check(c, launch_gather(st, w1, k2, n, ow), "pair sort gather");
+    sync(c, "pair sort");
+}
+
+// Hand a computed edge list (library-owned arrays `res`, n pairs) to the
+// caller's `out` under the capacity protocol: moved when out->capacity is 0,
+// copied into caller buffers otherwise (SLINE_ECAPACITY if too small).
+sline_status deliver(sline_ctx *c, OwnedEdges &res, sline_edges *out, bool weights) {
+    const int64_t n = res.e.n_pairs;
+    if (out->capacity > 0 && out->capacity < n) {
+        out->n_pairs = n;
+        set_err(c, "capacity too small");
+        return SLINE_ECAPACITY;
+    }
+    if (out->capacity == 0) {
+        if (n == 0) {
+            out->n_pairs = 0;
+            out->a = out->b = out->w = nullptr;
+            return SLINE_OK;
+        }
+        const sline_edges r = res.release();
+        out->n_pairs = n;
+        out->a = r.a;
+        out->b = r.b;
+        out->w = weights ? r.w : nullptr;
+        if (!weights && r.w) dev_free(c, r.w, sizeof(int32_t) * (size_t)n);
+        return SLINE_OK;
+    }
+    hipStream_t st = c->stream;
+    hip_check(c, launch_copy_i32(st, out->a, res.e.a, n), "copy result");
+    hip_check(c, launch_copy_i32(st, out->b, res.e.b, n), "copy result");
+    if (weights && out->w && res.e.w) hip_check(c, launch_copy_i32(st, out->w, res.e.w, n), "copy result");
+    sync(c, "copy result");
+    out->n_pairs = n;
+    return SLINE_OK;
+}
+
+// The CSR rules of sline_csr, checked on the device; returns nnz.
+int64_t validate_csr(sline_ctx *c, const sline_csr &H, uint32_t flags) {
+    hipStream_t st = c->stream;
+    const int64_t m = H.n_edges, n = H.n_vertices;
+    if (m > 0 && !H.row_ptr) {
+        set_err(c, "row_ptr is NULL");
+        throw Fail{SLINE_EINVAL};
+    }
+    TempBlock T0(c);
+    int32_t *err = reinterpret_cast<int32_t *>(T0.get(64, "flags"));
+    hip_check(c, launch_fill_i32(st, err, 4, 0), "zero flags");
+    int32_t *h = reinterpret_cast<int32_t *>(c->host);
+    h[0] = 0;
+    if (m > 0) {
+        hip_check(c, launch_check_rowptr(st, H.row_ptr, (int32_t)m, err), "row_ptr check");
+        hip_check(c, hipMemcpyAsync(h, H.row_ptr + m, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read nnz");
+    }
+    hip_check(c, hipMemcpyAsync(h + 1, err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "row_ptr check");
+    const int64_t nnz = h[0];
+    if (h[1] != 0 || nnz < 0) {
+        set_err(c, "row_ptr must start at 0 and never decrease");
+        throw Fail{SLINE_EINVAL};
+    }
+    if (nnz > 0 && (!H.col_idx || n == 0)) {
+        set_err(c, "col_idx is NULL or n_vertices is 0 with nnz > 0");
+        throw Fail{SLINE_EINVAL};
+    }
+    if (nnz > 0) {
+        TempBlock T1(c);
+        int32_t *rowid = reinterpret_cast<int32_t *>(T1.get(sizeof(int32_t) * (size_t)nnz, "row ids"));
+        hip_check(c, launch_rows(st, H.row_ptr, H.col_idx, (int32_t)m, (int32_t)n, nnz,
+                                 (flags & SLINE_SKIP_VALIDATE) ? 0 : 1, rowid, err),
+                  "row check");
+        hip_check(c, hipMemcpyAsync(h + 1, err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "row check");
+        if (h[1] & (kErrColRange | kErrColOrder)) {
+            set_err(c, "col_idx: members must lie in [0, n_vertices) and increase strictly within a row");
+            throw Fail{SLINE_EINVAL};
+        }
+    }
+    return nnz;
+}
+
+// sline_build with SLINE_RELABEL_*: renumber the side's items by size, build,
+// map the pairs back and sort them (Sec. IV-F).
+sline_status relabel_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dual,
+                          uint32_t flags, sline_edges *out) {
+    const bool desc = (flags & SLINE_RELABEL_DESC) != 0;
+    if ((flags & kRelabelFlags) == kRelabelFlags) {
+        set_err(c, "SLINE_RELABEL_DESC and SLINE_RELABEL_ASC exclude each other");
+        return SLINE_EINVAL;
+    }
+    const int64_t nnz = validate_csr(c, H, flags);
+    hipStream_t st = c->stream;
+    const int32_t m = H.n_edges, n = H.n_vertices;
+    const int32_t N = dual ? n : m;
+    const bool weights = !(flags & SLINE_NO_WEIGHTS);
+    // 1. sizes, the permutation (stable by size, ties by id) and its inverse
+    Arena sz;
+    auto plan = [&](Arena &A, int32_t *&size, int32_t *&mx, int32_t *&key, int32_t *&ids,
+                    int32_t *&perm, int32_t *&inv, SortBufs &B, int32_t *&ptrV, int32_t *&colV,
+                    SortBufs &BV) {
+        size = A.take<int32_t>(N);
+        mx = A.take<int32_t>(4);
+        key = A.take<int32_t>(N);
+        ids = A.take<int32_t>(N);
+        perm = A.take<int32_t>(N);
+        inv = A.take<int32_t>(N);
+        // sizes are at most max(nnz, 1); the key sort spans that many buckets
+        B = plan_sort(A, N, std::max<int64_t>(nnz, 1) + 1);
+        ptrV = nullptr;
+        colV = nullptr;
+        if (dual) {  // vertex degrees from the transpose of H
+            BV = plan_sort(A, std::max<int64_t>(nnz, 1), n);
+            ptrV = BV.ptrT;
+            colV = A.take<int32_t>(std::max<int64_t>(nnz, 1));
+        }
+    };
+    int32_t *size, *mx, *key, *ids, *perm, *inv, *ptrV, *colV;
+    SortBufs B{}, BV{};
+    plan(sz, size, mx, key, ids, perm, inv, B, ptrV, colV, BV);
+    TempBlock T(c);
+    Arena A;
+    A.base = T.get(sz.off, "relabel");
+    plan(A, size, mx, key, ids, perm, inv, B, ptrV, colV, BV);
+    hip_check(c, launch_fill_i32(st, mx, 4, 0), "zero max");
+    const int32_t *item_ptr = H.row_ptr;
+    if (dual) {
+        TempBlock TR(c);
+        int32_t *rowid = reinterpret_cast<int32_t *>(TR.get(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1), "row ids"));
+        hip_check(c, launch_row_ids(st, H.row_ptr, m, rowid), "row ids");
+        hip_check(c, launch_transpose(st, H.col_idx, nnz, n, rowid, BV.rsK, BV.rsV, BV.hist, BV.part32,
+                                      BV.ptrT, colV, nullptr, nullptr),
+                  "vertex lists");
+        item_ptr = ptrV;
+        sync(c, "vertex lists");
+    }
+    hip_check(c, launch_sizes(st, item_ptr, N, size, mx), "item sizes");
+    hip_check(c, hipMemcpyAsync(c->host, mx, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read max size");
+    sync(c, "item sizes");
+    const int32_t max_size = reinterpret_cast<const int32_t *>(c->host)[0];
+    hip_check(c, launch_size_keys(st, size, N, mx, desc ? 1 : 0, key), "size keys");
+    hip_check(c, launch_iota(st, ids, N), "ids");
+    if (N > 0)
+        hip_check(c, launch_transpose(st, key, N, max_size + 1, ids, B.rsK, B.rsV, B.hist, B.part32,
+                                      B.ptrT, perm, nullptr, nullptr),
+                  "size order");
+    hip_check(c, launch_invert(st, perm, N, inv), "inverse order");
+    // 2. the renumbered hypergraph
+    TempBlock TH(c);
+    sline_csr H2 = H;
+    {
+        Arena hs;
+        hs.take<int32_t>((int64_t)m + 1);
+        hs.take<int32_t>(std::max<int64_t>(nnz, 1));
+        hs.take<int32_t>(std::max<int64_t>(N, 1));
+        hs.take<int32_t>(std::max<int64_t>(nnz, 1));
+        hs.take<int32_t>(std::max<int64_t>(nnz, 1));
+        hs.take<int32_t>(std::max<int64_t>(nnz, 1));
+        Arena ha;
+        ha.base = TH.get(hs.off, "relabeled hypergraph");
+        int32_t *nrp = ha.take<int32_t>((int64_t)m + 1);
+        int32_t *ncol = ha.take<int32_t>(std::max<int64_t>(nnz, 1));
+        int32_t *len = ha.take<int32_t>(std::max<int64_t>(N, 1));
+        int32_t *rowid = ha.take<int32_t>(std::max<int64_t>(nnz, 1));
+        int32_t *rcol = ha.take<int32_t>(std::max<int64_t>(nnz, 1));
+        int32_t *rrow = ha.take<int32_t>(std::max<int64_t>(nnz, 1));
+        if (!dual) {
+            // rows in the new order
+            hip_check(c, launch_perm_rows(st, H.row_ptr, H.col_idx, perm, m, len, nrp, B.part32, ncol),
+                      "relabeled rows");
+            H2.row_ptr = nrp;
+            H2.col_idx = ncol;
+        } else if (nnz > 0) {
+            // vertex ids renumbered, every row sorted again
+            hip_check(c, launch_row_ids(st, H.row_ptr, m, rowid), "row ids");
+            hip_check(c, launch_gather(st, inv, H.col_idx, nnz, rcol), "renumbered members");
+            sort_pairs(c, rowid, rcol, nullptr, nnz, std::max(m, n), rrow, ncol, nullptr);
+            H2.col_idx = ncol;
+        }
+        sync(c, "relabeled hypergraph");
+        // 3. build on it, 4. map back and sort
+        OwnedEdges tmp(c);
+        ItemS IS;
+        IS.s_min = IS.s_max = s;
+        sline_edges t{};
+        const sline_status r = build_core(c, H2, s, dual, (flags & ~kRelabelFlags) | SLINE_SKIP_VALIDATE,
+                                          &t, IS);
+        tmp.e = t;
+        if (r != SLINE_OK) return r;
+        const int64_t np = t.n_pairs;
+        if (np >= INT32_MAX) {
+            set_err(c, "relabeled builds handle results below 2^31 pairs");
+            return SLINE_EINVAL;
+        }
+        OwnedEdges res(c);
+        res.alloc(np, weights, "relabeled result");
+        if (np > 0) {
+            TempBlock TM(c);
+            Arena ms;
+            ms.take<int32_t>(np);
+            ms.take<int32_t>(np);
+            Arena ma;
+            ma.base = TM.get(ms.off, "mapped pairs");
+            int32_t *x = ma.take<int32_t>(np);
+            int32_t *y = ma.take<int32_t>(np);
+            hip_check(c, launch_map_pairs(st, t.a, t.b, np, perm, x, y), "map back");
+            sort_pairs(c, x, y, weights ? t.w : nullptr, np, N, res.e.a, res.e.b,
+                       weights ? res.e.w : nullptr);
+        }
+        const sline_stats keep = c->stats;
+        const sline_status d = deliver(c, res, out, weights);
+        c->stats = keep;
+        return d;
+    }
+}
+
+// sline_build with SLINE_NO_VISITED: one set intersection per wedge, the
+// accepted pairs written per item in any order, then sorted.  Called by
+// build_core once the member lists, back-pointers and costs are ready.
+sline_status intersect_build(sline_ctx *c, const int32_t *ptrI, const int32_t *memI,
+                             const int32_t *ptrS, const int32_t *itmS, const int32_t *start,
+                             int32_t N, int32_t s, uint32_t flags, int32_t *cnt, int64_t *off,
+                             int64_t *part64, unsigned long long *inters, sline_edges *out,
+                             sline_stats &S) {
+    hipStream_t st = c->stream;
+    const bool prune = !(flags & SLINE_NO_PRUNE);
+    const bool shortcut = !(flags & SLINE_NO_SHORTCUT);
+    const bool weights = !(flags & SLINE_NO_WEIGHTS);
+    hip_check(c, launch_fill_i32(st, cnt, N, 0), "zero counts");
+    mark(c, 2);
+    hip_check(c, launch_wedge_intersect(st, ptrI, memI, ptrS, itmS, start, N, s, prune ? 1 : 0,
+                                        shortcut ? 1 : 0, cnt, nullptr, nullptr, nullptr, nullptr,
+                                        inters, c->n_cu),
+              "intersections (count)");
+    hip_check(c, launch_scan_i32_to_i64(st, cnt, N, off, part64), "pair scan");
+    mark(c, 3);
+    int64_t *h = c->host;
+    hip_check(c, hipMemcpyAsync(h, off + N, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read total");
+    hip_check(c, hipMemcpyAsync(h + 1, inters, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+              "read intersections");
+    sync(c, "intersections");
+    const int64_t total = h[0];
+    S.intersections = h[1];
+    S.n_pairs = total;
+    if (c->profile) S.ms_count = span_ms(c, 2, 3);
+    c->stats = S;
+    if (total >= INT32_MAX) {
+        set_err(c, "builds without visited skipping handle results below 2^31 pairs");
+        return SLINE_EINVAL;
+    }
+    if (out->capacity > 0 && out->capacity < total) {
+        out->n_pairs = total;
+        set_err(c, "capacity too small");
+        return SLINE_ECAPACITY;
+    }
+    OwnedEdges raw(c), res(c);
+    raw.alloc(total, true, "unsorted pairs");
+    res.alloc(total, weights, "result");
+    mark(c, 5);
+    if (total > 0) {
+        hip_check(c, launch_wedge_intersect(st, ptrI, memI, ptrS, itmS, start, N, s, prune ? 1 : 0,
+                                            shortcut ? 1 : 0, cnt, off, raw.e.a, raw.e.b, raw.e.w,
+                                            nullptr, c->n_cu),
+                  "intersections (write)");
+        sort_pairs(c, raw.e.a, raw.e.b, raw.e.w, total, N, res.e.a, res.e.b,
+                   weights ? res.e.w : nullptr);
+    }
+    mark(c, 6);
+    sync(c, "intersections");
+    if (c->profile) S.ms_fill = span_ms(c, 5, 6);
+    c->stats = S;
+    return deliver(c, res, out, weights);
+}
+
+sline_status filter_impl(sline_ctx *c, const sline_edges *in, int32_t s, uint32_t flags,
+                         sline_edges *out) {
+    if (!in || !out || s < 1 || in->n_pairs < 0 ||
+        (in->n_pairs > 0 && (!in->a || !in->b || !in->w))) {
+        set_err(c, "invalid arguments (s >= 1 and an input with a, b and w required)");
+        return SLINE_EINVAL;
+    }
+    if (out->capacity < 0 ||
+        (out->capacity > 0 && (!out->a || !out->b || (!out->w && !(flags & SLINE_NO_WEIGHTS))))) {
+        set_err(c, "output buffers: capacity > 0 requires a, b and (without SLINE_NO_WEIGHTS) w");
+        return SLINE_EINVAL;
+    }
+    c->pending.valid = false;
+    hipStream_t st = c->stream;
+    const int64_t n = in->n_pairs;
+    const bool weights = !(flags & SLINE_NO_WEIGHTS);
+    const int64_t tiles = wfilter_tiles(n);
+    int64_t total = 0;
+    TempBlock T(c);
+    int32_t *cnt = nullptr;
+    int64_t *off = nullptr;
+    if (n > 0) {
+        Arena sz;
+        sz.take<int32_t>(tiles);
+        sz.take<int64_t>(tiles + 1);
+        sz.take<int64_t>(scan_partials(tiles + 1));
+        Arena A;
+        A.base = T.get(sz.off, "filter");
+        cnt = A.take<int32_t>(tiles);
+        off = A.take<int64_t>(tiles + 1);
+        int64_t *part = A.take<int64_t>(scan_partials(tiles + 1));
+        hip_check(c, launch_wfilter(st, in->a, in->b, in->w, n, s, cnt, nullptr, nullptr, nullptr,
+                                    nullptr),
+                  "filter count");
+        hip_check(c, launch_scan_i32_to_i64(st, cnt, tiles, off, part), "filter scan");
+        hip_check(c, hipMemcpyAsync(c->host, off + tiles, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+                  "read filtered size");
+        sync(c, "filter count");
+        total = c->host[0];
+    }
+    if (out->capacity > 0 && out->capacity < total) {
+        out->n_pairs = total;
+        set_err(c, "capacity too small");
+        return SLINE_ECAPACITY;
+    }
+    OwnedEdges res(c);
+    int32_t *oa = out->a, *ob = out->b, *ow = weights ? out->w : nullptr;
+    if (out->capacity == 0 && total > 0) {
+        res.alloc(total, weights, "filtered pairs");
+        oa = res.e.a;
+        ob = res.e.b;
+        ow = res.e.w;
+    }
+    if (total > 0) {
+        hip_check(c, launch_wfilter(st, in->a, in->b, in->w, n, s, cnt, off, oa, ob, ow),
+                  "filter write");
+        sync(c, "filter write");
+    }
+    if (out->capacity == 0) {
+        const sline_edges r = res.release();
+        out->a = total ? r.a : nullptr;
+        out->b = total ? r.b : nullptr;
+        out->w = total ? r.w : nullptr;
+    }
+    out->n_pairs = total;
+    return SLINE_OK;
+}
+
+sline_status sweep_impl(sline_ctx *c, const sline_csr &H, int32_t n_s, const int32_t *s_list,
+                        int32_t dual, uint32_t flags, sline_edges *outs) {
+    if (n_s < 0 || (n_s > 0 && (!s_list || !outs)) || (dual != 0 && dual != 1) ||
+        (flags & SLINE_NO_WEIGHTS)) {
+        set_err(c, "invalid sweep arguments (s_list and outs of n_s entries; no SLINE_NO_WEIGHTS)");
+        return SLINE_EINVAL;
+    }
+    for (int32_t i = 0; i < n_s; ++i) {
+        if (s_list[i] < 1 || outs[i].capacity != 0) {
+            set_err(c, "every s >= 1, every output with capacity 0");
+            return SLINE_EINVAL;
+        }
+    }
+    if (n_s == 0) return SLINE_OK;
+    std::vector<int32_t> order(n_s);
+    for (int32_t i = 0; i < n_s; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return s_list[x] < s_list[y]; });
+    std::vector<sline_edges> res(n_s);
+    auto release_all = [&]() {
+        for (auto &e : res) {
+            if (e.a || e.b || e.w) (void)sline_edges_free(c, &e);
+        }
+    };
+    sline_status r = build_impl(c, H, s_list[order[0]], dual, flags, &res[order[0]]);
+    if (r != SLINE_OK) return r;
+    try {
+        for (int32_t k = 1; k < n_s; ++k) {
+            const sline_edges &prev = res[order[k - 1]];
+            r = filter_impl(c, &prev, s_list[order[k]], flags, &res[order[k]]);
+            if (r != SLINE_OK) {
+                release_all();
+                return r;
+            }
+        }
+    } catch (...) {
+        release_all();
+        throw;
+    }
+    for (int32_t i = 0; i < n_s; ++i) outs[i] = res[i];
+    return SLINE_OK;
+}
+
+sline_status squeeze_impl(sline_ctx *c, int32_t N, const sline_edges *L, uint32_t flags,
+                          sline_graph *G) {
+    const bool weights = !(flags & SLINE_NO_WEIGHTS);
+    if (!L || !G || N < 0 || L->n_pairs < 0 || L->n_pairs >= INT32_MAX ||
+        (L->n_pairs > 0 && (!L->a || !L->b || (weights && !L->w)))) {
+        set_err(c, "invalid arguments (pairs with a, b and w unless SLINE_NO_WEIGHTS; "
+                   "n_pairs below 2^31)");
+        return SLINE_EINVAL;
+    }
+    hipStream_t st = c->stream;
+    const int64_t n = L->n_pairs;
+    sline_graph g{};
+    auto plan = [&](Arena &A, int32_t *&err, int32_t *&flag, int32_t *&newid, int32_t *&p32,
+                    int64_t *&fwd, int32_t *&deg, int64_t *&off, int64_t *&p64, SortBufs &B,
+                    int32_t *&colT, int32_t *&kT) {
+        err = A.take<int32_t>(4);
+        flag = A.take<int32_t>((int64_t)N + 1);
+        newid = A.take<int32_t>((int64_t)N + 1);
+        p32 = A.take<int32_t>(scan_partials((int64_t)N + 1));
+        fwd = A.take<int64_t>((int64_t)N + 1);
+        deg = A.take<int32_t>((int64_t)N + 1);
+        off = A.take<int64_t>((int64_t)N + 1);
+        p64 = A.take<int64_t>(scan_partials((int64_t)N + 1));
+        B = plan_sort(A, std::max<int64_t>(n, 1), N);
+        colT = A.take<int32_t>(std::max<int64_t>(n, 1));
+        kT = A.take<int32_t>(std::max<int64_t>(n, 1));
+    };
+    int32_t *err, *flag, *newid, *p32, *deg, *colT, *kT;
+    int64_t *fwd, *off, *p64;
+    SortBufs B{};
+    Arena sz;
+    plan(sz, err, flag, newid, p32, fwd, deg, off, p64, B, colT, kT);
+    TempBlock T(c);
+    Arena A;
+    A.base = T.get(sz.off, "squeeze");
+    plan(A, err, flag, newid, p32, fwd, deg, off, p64, B, colT, kT);
+    hip_check(c, launch_fill_i32(st, err, 4, 0), "zero flags");
+    hip_check(c, launch_fill_i32(st, flag, (int64_t)N + 1, 0), "zero flags");
+    // 1. items present (and the pairs checked: ids in range, a < b, sorted)
+    hip_check(c, launch_mark_present(st, L->a, L->b, n, N, flag, err), "items present");
+    hip_check(c, hipMemcpyAsync(c->host, err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "items present");
+    if (reinterpret_cast<const int32_t *>(c->host)[0]) {
+        set_err(c, "pairs must have 0 <= a < b < n_items and be sorted by (a, b)");
+        return SLINE_EINVAL;
+    }
+    // 2. new ids: exclusive scan of the presence flags
+    hip_check(c, launch_scan_i32(st, flag, N, newid, p32), "new ids");
+    hip_check(c, hipMemcpyAsync(c->host, newid + N, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+              "read node count");
+    sync(c, "new ids");
+    g.n_nodes = reinterpret_cast<const int32_t *>(c->host)[0];
+    g.n_arcs = 2 * n;
+    auto free_graph = [&]() {
+        (void)hipStreamSynchronize(st);
+        dev_free(c, g.old_id, sizeof(int32_t) * (size_t)std::max(g.n_nodes, 1));
+        dev_free(c, g.row_ptr, sizeof(int64_t) * ((size_t)g.n_nodes + 1));
+        dev_free(c, g.col, sizeof(int32_t) * (size_t)std::max<int64_t>(g.n_arcs, 1));
+        dev_free(c, g.w, sizeof(int32_t) * (size_t)std::max<int64_t>(g.n_arcs, 1));
+    };
+    try {
+        g.old_id = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)std::max(g.n_nodes, 1));
+        g.row_ptr = (int64_t *)dev_alloc(c, sizeof(int64_t) * ((size_t)g.n_nodes + 1));
+        g.col = (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)std::max<int64_t>(g.n_arcs, 1));
+        g.w = weights ? (int32_t *)dev_alloc(c, sizeof(int32_t) * (size_t)std::max<int64_t>(g.n_arcs, 1))
+                      : nullptr;
+        if (!g.old_id || !g.row_ptr || !g.col || (weights && !g.w)) {
+            set_err(c, "graph allocation failed");
+            throw Fail{SLINE_ENOMEM};
+        }
+        hip_check(c, launch_old_ids(st, flag, newid, N, g.old_id), "old ids");
+        // 3. the pairs by second item (transpose), by first item (runs)
+        hip_check(c, launch_transpose(st, L->b, n, N, L->a, B.rsK, B.rsV, B.hist, B.part32, B.ptrT,
+                                      colT, kT, nullptr),
+                  "pairs by second item");
+        hip_check(c, launch_run_starts(st, L->a, n, N, fwd), "pairs by first item");
+        // 4. degrees, row pointers, rows
+        hip_check(c, launch_degrees(st, fwd, B.ptrT, N, deg), "degrees");
+        hip_check(c, launch_scan_i32_to_i64(st, deg, N, off, p64), "row offsets");
+        hip_check(c, launch_row_ptr(st, flag, newid, off, N, g.n_nodes, g.row_ptr), "row pointers");
+        hip_check(c, launch_adj_fill(st, N, flag, newid, off, B.ptrT, colT, kT, fwd, L->b,
+                                     weights ? L->w : nullptr, g.col, g.w),
+                  "adjacency");
+        sync(c, "adjacency");
+    } catch (...) {
+        free_graph();
+        throw;
+    }
+    *G = g;
+    return SLINE_OK;
+}
+
+sline_status components_impl(sline_ctx *c, int32_t N, const sline_edges *L, int32_t *comp,
+                             int64_t *n_components) {
+    if (!L || N < 0 || L->n_pairs < 0 || (N > 0 && !comp) ||
+        (L->n_pairs > 0 && (!L->a || !L->b))) {
+        set_err(c, "invalid arguments");
+        return SLINE_EINVAL;
+    }
+    hipStream_t st = c->stream;
+    const int64_t n = L->n_pairs;
+    TempBlock T(c);
+    Arena sz;
+    sz.take<int32_t>(4);
+    sz.take<unsigned long long>(1);
+    sz.take<int32_t>((int64_t)N + 1);
+    Arena A;
+    A.base = T.get(sz.off, "components");
+    int32_t *err = A.take<int32_t>(4);
+    unsigned long long *count = A.take<unsigned long long>(1);
+    int32_t *flag = A.take<int32_t>((int64_t)N + 1);
+    hip_check(c, launch_fill_i32(st, err, 4, 0), "zero flags");
+    hip_check(c, launch_fill_i64(st, reinterpret_cast<int64_t *>(count), 1, 0), "zero count");
+    hip_check(c, launch_fill_i32(st, flag, (int64_t)N + 1, 0), "zero flags");
+    hip_check(c, launch_mark_present(st, L->a, L->b, n, N, flag, err), "items present");
+    hip_check(c, hipMemcpyAsync(c->host, err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
+    sync(c, "items present");
+    if (reinterpret_cast<const int32_t *>(c->host)[0]) {
+        set_err(c, "pairs must have 0 <= a < b < n_items and be sorted by (a, b)");
+        return SLINE_EINVAL;
+    }
+    hip_check(c, launch_components(st, L->a, L->b, n, N, comp), "components");
+    hip_check(c, launch_cc_count(st, comp, flag, N, count), "component count");
+    hip_check(c, hipMemcpyAsync(c->host, count, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+              "read component count");
+    sync(c, "components");
+    if (n_components) *n_components = c->host[0];
+    return SLINE_OK;
+}
+
+// Entry-point wrapper: device, error capture.
+template <typename F>
+sline_status guarded(sline_ctx *c, F &&f) {
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return f();
+    } catch (const Fail &fl) {
+        c->pending.valid = false;
+        release_pool(c);
+        return fl.st;
+    } catch (const std::bad_alloc &) {
+        c->pending.valid = false;
+        release_pool(c);
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
 }
 
 }  // namespace
@@ -1631,5 +2340,41 @@ const char *sline_status_str(sline_status s) {
 }
 
 const char *sline_last_error(sline_ctx *c) { return c ? c->last_error.c_str() : "no context"; }
+
+}  // extern "C"
+
+extern "C" {
+
+sline_status sline_filter(sline_ctx *c, const sline_edges *in, int32_t s, uint32_t flags,
+                          sline_edges *out) {
+    return guarded(c, [&]() { return filter_impl(c, in, s, flags, out); });
+}
+
+sline_status sline_build_sweep(sline_ctx *c, sline_csr H, int32_t n_s, const int32_t *s_list,
+                               int32_t dual, uint32_t flags, sline_edges *outs) {
+    return guarded(c, [&]() { return sweep_impl(c, H, n_s, s_list, dual, flags, outs); });
+}
+
+sline_status sline_squeeze(sline_ctx *c, int32_t n_items, const sline_edges *L, uint32_t flags,
+                           sline_graph *G) {
+    return guarded(c, [&]() { return squeeze_impl(c, n_items, L, flags, G); });
+}
+
+sline_status sline_graph_free(sline_ctx *c, sline_graph *G) {
+    if (!c || !G) return SLINE_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, G->old_id, sizeof(int32_t) * (size_t)std::max(G->n_nodes, 1));
+    dev_free(c, G->row_ptr, sizeof(int64_t) * ((size_t)G->n_nodes + 1));
+    dev_free(c, G->col, sizeof(int32_t) * (size_t)std::max<int64_t>(G->n_arcs, 1));
+    dev_free(c, G->w, sizeof(int32_t) * (size_t)std::max<int64_t>(G->n_arcs, 1));
+    (void)hipStreamSynchronize(c->stream);
+    *G = sline_graph{};
+    return SLINE_OK;
+}
+
+sline_status sline_components(sline_ctx *c, int32_t n_items, const sline_edges *L, int32_t *comp,
+                              int64_t *n_components) {
+    return guarded(c, [&]() { return components_impl(c, n_items, L, comp, n_components); });
+}
 
 }  // extern "C"

@@ -71,6 +71,9 @@ hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map
 // hist holds 16 * transpose_tiles(nnz) + 1 counts and part32 the partials of
 // their scan.
 int64_t transpose_tiles(int64_t nnz);
+// Radix passes of a transpose over members in [0, n); its sorted members end
+// in rsK[(passes - 1) & 1].
+int transpose_passes(int32_t n);
 hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
                             const int32_t *rowid, int32_t *const rsK[2], int32_t *const rsV[2],
                             int32_t *hist, int32_t *part32, int32_t *ptrT, int32_t *colT,
@@ -239,5 +242,59 @@ hipError_t launch_batch_graph_off(hipStream_t st, const int32_t *task_item, int3
 
 // Copy staged ranges to their final place (skipping tasks flagged in need).
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);
+
+// ------------------------------------------------- stages (sline_stages.hip)
+// Filter of a weighted edge list: pairs with w >= s, in order.  Pass 1
+// (oa == nullptr) writes per-tile counts, pass 2 writes at the exclusive scan
+// off of those counts.
+int64_t wfilter_tiles(int64_t n);
+hipError_t launch_wfilter(hipStream_t st, const int32_t *a, const int32_t *b, const int32_t *w,
+                          int64_t n, int32_t s, int32_t *cnt, const int64_t *off, int32_t *oa,
+                          int32_t *ob, int32_t *ow);
+// flag[x] = 1 for items in a pair (flag zeroed by the caller); err gets
+// kErrColRange for an id out of [0, N) or a >= b, kErrColOrder for pairs out
+// of (a, b) order.
+hipError_t launch_mark_present(hipStream_t st, const int32_t *a, const int32_t *b, int64_t n,
+                               int32_t N, int32_t *flag, int32_t *err);
+hipError_t launch_old_ids(hipStream_t st, const int32_t *flag, const int32_t *newid, int32_t N,
+                          int32_t *old_id);
+// ptr[x] (x = 0..N) = first pair with a >= x, for pairs sorted by a.
+hipError_t launch_run_starts(hipStream_t st, const int32_t *a, int64_t n, int32_t N, int64_t *ptr);
+hipError_t launch_degrees(hipStream_t st, const int64_t *fwd, const int32_t *ptrT, int32_t N,
+                          int32_t *deg);
+hipError_t launch_row_ptr(hipStream_t st, const int32_t *flag, const int32_t *newid,
+                          const int64_t *off, int32_t N, int32_t n_nodes, int64_t *row_ptr);
+hipError_t launch_adj_fill(hipStream_t st, int32_t N, const int32_t *flag, const int32_t *newid,
+                           const int64_t *off, const int32_t *ptrT, const int32_t *colT,
+                           const int32_t *kT, const int64_t *fwd, const int32_t *b,
+                           const int32_t *w, int32_t *ocol, int32_t *ow);
+hipError_t launch_iota(hipStream_t st, int32_t *p, int64_t n);
+// comp[x] = smallest item of x's component in the graph of the pairs.
+hipError_t launch_components(hipStream_t st, const int32_t *a, const int32_t *b, int64_t n,
+                             int32_t N, int32_t *comp);
+hipError_t launch_cc_count(hipStream_t st, const int32_t *comp, const int32_t *flag, int32_t N,
+                           unsigned long long *count);
+hipError_t launch_gather(hipStream_t st, const int32_t *src, const int32_t *idx, int64_t n,
+                         int32_t *dst);
+hipError_t launch_map_pairs(hipStream_t st, const int32_t *a, const int32_t *b, int64_t n,
+                            const int32_t *perm, int32_t *oa, int32_t *ob);
+hipError_t launch_sizes(hipStream_t st, const int32_t *ptr, int32_t N, int32_t *size,
+                        int32_t *max_size);
+hipError_t launch_size_keys(hipStream_t st, const int32_t *size, int32_t N, const int32_t *max_size,
+                            int32_t descending, int32_t *key);
+hipError_t launch_invert(hipStream_t st, const int32_t *perm, int32_t N, int32_t *inv);
+// Rows of (rp, col) in the order perm: nrp (N + 1, len and part32 scratch), ncol.
+hipError_t launch_perm_rows(hipStream_t st, const int32_t *rp, const int32_t *col,
+                            const int32_t *perm, int32_t N, int32_t *len, int32_t *nrp,
+                            int32_t *part32, int32_t *ncol);
+hipError_t launch_row_ids(hipStream_t st, const int32_t *rp, int32_t m, int32_t *rowid);
+// One set intersection per wedge (the variants without visited skipping):
+// count mode (oa == nullptr) writes each item's accepted pairs to cnt, write
+// mode appends them from off[a]; inters (nullable) adds the intersections.
+hipError_t launch_wedge_intersect(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
+                                  const int32_t *ptrS, const int32_t *itmS, const int32_t *start,
+                                  int32_t N, int32_t s, int32_t prune, int32_t shortcut,
+                                  int32_t *cnt, const int64_t *off, int32_t *oa, int32_t *ob,
+                                  int32_t *ow, unsigned long long *inters, int32_t n_cu);
 
 }  // namespace sl

@@ -683,14 +683,18 @@ hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map
 
 int64_t transpose_tiles(int64_t nnz) { return (nnz + kRsTile - 1) / kRsTile; }
 
+int transpose_passes(int32_t n) {
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+    return std::max(1, (bits + kRsBits - 1) / kRsBits);
+}
+
 hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int32_t n,
                             const int32_t *rowid, int32_t *const rsK[2], int32_t *const rsV[2],
                             int32_t *hist, int32_t *part32, int32_t *ptrT, int32_t *colT,
                             int32_t *kT, int32_t *posT) {
     if (nnz <= 0) return launch_fill_i32(st, ptrT, (int64_t)n + 1, 0);
-    int bits = 0;
-    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
-    const int passes = std::max(1, (bits + kRsBits - 1) / kRsBits);
+    const int passes = transpose_passes(n);
     const int32_t ntiles = (int32_t)transpose_tiles(nnz);
     hipError_t e = hipSuccess;
     for (int p = 0; p < passes && e == hipSuccess; ++p) {

@@ -27,6 +27,15 @@ SLINE_EBUSY = -5
 SLINE_SKIP_VALIDATE = 1
 SLINE_PROFILE = 2
 SLINE_NO_WEIGHTS = 4
+SLINE_RELABEL_DESC = 8
+SLINE_RELABEL_ASC = 16
+SLINE_NO_PRUNE = 32
+SLINE_NO_VISITED = 64
+SLINE_NO_SHORTCUT = 128
+# the variants of Table III as sline_build flags
+VARIANT_FLAGS = {"f0": 0, "f1": SLINE_NO_VISITED | SLINE_NO_SHORTCUT,
+                 "f2": SLINE_NO_PRUNE | SLINE_NO_SHORTCUT, "f3": SLINE_NO_PRUNE | SLINE_NO_VISITED,
+                 "f4": SLINE_NO_PRUNE | SLINE_NO_VISITED | SLINE_NO_SHORTCUT}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
@@ -48,7 +57,8 @@ class sline_stats(ctypes.Structure):
                 ("ms_transpose", "ms_prepare", "ms_count", "ms_scan", "ms_fill")] + [
                 (k, ctypes.c_int64) for k in ("heavy_nnz", "heavy_wedges", "heavy_pairs")] + [
                 ("ms_tasks", ctypes.c_double), ("product_nnz", ctypes.c_int64),
-                ("ms_product", ctypes.c_double), ("ms_filter", ctypes.c_double)]
+                ("ms_product", ctypes.c_double), ("ms_filter", ctypes.c_double),
+                ("intersections", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: (float(getattr(self, k)) if k.startswith("ms_") else int(getattr(self, k)))
@@ -63,6 +73,12 @@ class sline_tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class sline_graph(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_arcs", ctypes.c_int64),
+                ("old_id", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p)]
 
 
 class sline_query_info(ctypes.Structure):
@@ -108,6 +124,17 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
                                            ctypes.POINTER(sline_edges)]),
     "sline_edges_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
+    "sline_filter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges), ctypes.c_int32,
+                                      ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
+    "sline_build_sweep": (ctypes.c_int32, [ctypes.c_void_p, sline_csr, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                           ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
+    "sline_squeeze": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(sline_edges),
+                                       ctypes.c_uint32, ctypes.POINTER(sline_graph)]),
+    "sline_graph_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_graph)]),
+    "sline_components": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(sline_edges), ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_int64)]),
     "sline_last_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_stats)]),
     "sline_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
     "sline_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_tuning)]),
@@ -403,6 +430,88 @@ class Context:
         return [LineGraph(bufs[g][0, :need[g]], bufs[g][1, :need[g]], bufs[g][2, :need[g]])
                 for g in range(G)]
 
+    # ------------------------------------------------ after L_s (Table I)
+
+    @staticmethod
+    def edges_of(L: "LineGraph") -> sline_edges:
+        """An sline_edges view (capacity 0) of a LineGraph's device tensors."""
+        n = len(L)
+        ptr = lambda t: (t.data_ptr() if (t is not None and t.numel()) else None)
+        return sline_edges(n, 0, ptr(L.a), ptr(L.b), ptr(L.w))
+
+    def _take(self, out: sline_edges, weights: bool = True) -> LineGraph:
+        """Copy a library-allocated result into torch tensors and free it."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        n = int(out.n_pairs)
+
+        def col(ptr):
+            if n == 0 or not ptr:
+                return torch.empty(0, dtype=torch.int32, device=dev)
+            return torch.as_tensor(_DeviceArray(ptr, n), device=dev).clone()
+
+        L = LineGraph(col(out.a), col(out.b), col(out.w) if weights else None)
+        torch.cuda.synchronize(dev)
+        sline_edges_free(self.ctx, out)
+        return L
+
+    def filter(self, L: LineGraph, s: int, flags: int = 0) -> LineGraph:
+        """L_s from a weighted L_s' (s' <= s): sline_filter."""
+        src = self.edges_of(L)
+        out = sline_edges()
+        st = load().sline_filter(self.ctx, ctypes.byref(src), s, flags, ctypes.byref(out))
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return self._take(out, not (flags & SLINE_NO_WEIGHTS))
+
+    def build_sweep(self, row_ptr, col, n_vertices: int, s_list, dual: int = 0,
+                    flags: int = 0) -> list[LineGraph]:
+        """L_s for every s of s_list, only the smallest counted (sline_build_sweep)."""
+        n = len(s_list)
+        outs = (sline_edges * max(n, 1))()
+        sarr = (ctypes.c_int32 * max(n, 1))(*[int(x) for x in s_list])
+        st = load().sline_build_sweep(self.ctx, self.csr(row_ptr, col, n_vertices), n, sarr, dual,
+                                      flags, outs)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return [self._take(outs[i]) for i in range(n)]
+
+    def squeeze(self, L: LineGraph, n_items: int, flags: int = 0) -> dict:
+        """ID squeezing and the symmetric adjacency (sline_squeeze), as torch tensors."""
+        import torch
+        src = self.edges_of(L)
+        g = sline_graph()
+        st = load().sline_squeeze(self.ctx, n_items, ctypes.byref(src), flags, ctypes.byref(g))
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        dev = torch.device("cuda", self.device)
+
+        def view(ptr, n, typestr, dtype):
+            if n == 0 or not ptr:
+                return torch.empty(0, dtype=dtype, device=dev)
+            return torch.as_tensor(_DeviceArray(ptr, n, typestr), device=dev).clone()
+
+        out = {"n_nodes": int(g.n_nodes), "n_arcs": int(g.n_arcs),
+               "old_id": view(g.old_id, g.n_nodes, "<i4", torch.int32),
+               "row_ptr": view(g.row_ptr, g.n_nodes + 1, "<i8", torch.int64),
+               "col": view(g.col, g.n_arcs, "<i4", torch.int32),
+               "w": None if flags & SLINE_NO_WEIGHTS else view(g.w, g.n_arcs, "<i4", torch.int32)}
+        torch.cuda.synchronize(dev)
+        load().sline_graph_free(self.ctx, ctypes.byref(g))
+        return out
+
+    def components(self, L: LineGraph, n_items: int):
+        """s-connected components (sline_components): (comp tensor, count)."""
+        import torch
+        comp = torch.empty(max(n_items, 1), dtype=torch.int32, device=torch.device("cuda", self.device))
+        src = self.edges_of(L)
+        cnt = ctypes.c_int64()
+        st = load().sline_components(self.ctx, n_items, ctypes.byref(src), comp.data_ptr(),
+                                     ctypes.byref(cnt))
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx))
+        return comp[:n_items], int(cnt.value)
+
     def stats(self) -> dict:
         return sline_last_stats(self.ctx).as_dict()
 
@@ -423,10 +532,10 @@ class Context:
 # -------------------------------------------------------------- serving
 
 class _DeviceArray:
-    """Zero-copy view of a device int32 array for torch.as_tensor."""
+    """Zero-copy view of a device array (int32 by default) for torch.as_tensor."""
 
-    def __init__(self, ptr: int, n: int):
-        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i4", "data": (ptr, False),
+    def __init__(self, ptr: int, n: int, typestr: str = "<i4"):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
                                          "version": 2, "strides": None}
 
 

@@ -63,6 +63,7 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
     out = sline.sline_edges()
     csr = sline.sline_csr()
     i32, i64 = ctypes.c_int32(0), ctypes.c_int64(0)
+    graph = sline.sline_graph()
     srv = ctypes.c_void_p()
     calls = {
         "sline_create": lambda: lib.sline_create(None, 0, None, None),
@@ -73,6 +74,12 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
         "sline_build_spgemm": lambda: lib.sline_build_spgemm(None, csr, 1, 0, 0,
                                                              ctypes.byref(out)),
         "sline_edges_free": lambda: lib.sline_edges_free(None, ctypes.byref(out)),
+        "sline_filter": lambda: lib.sline_filter(None, ctypes.byref(out), 1, 0, ctypes.byref(out)),
+        "sline_build_sweep": lambda: lib.sline_build_sweep(None, csr, 0, None, 0, 0, None),
+        "sline_squeeze": lambda: lib.sline_squeeze(None, 0, ctypes.byref(out), 0,
+                                                   ctypes.byref(graph)),
+        "sline_graph_free": lambda: lib.sline_graph_free(None, ctypes.byref(graph)),
+        "sline_components": lambda: lib.sline_components(None, 0, ctypes.byref(out), None, None),
         "sline_last_stats": lambda: lib.sline_last_stats(None, None),
         "sline_get_tuning": lambda: lib.sline_get_tuning(None, None),
         "sline_set_tuning": lambda: lib.sline_set_tuning(None, None),
