@@ -31,7 +31,12 @@ The one JSON line carries, beside ``value``:
   throughput at saturation, and the same queries run back to back with one
   plain call each.
 
-``--plain-only`` skips the last three.  Other forms (--form): ``dual`` (the
+* ``stages`` -- the rows after L_s: the s-sweep against plain builds,
+  squeezing and components per s, relabel-by-degree both ways, and the
+  variants f0..f4 of Table III at 1/20 scale with the oracle's heuristic
+  algorithm timed beside them.
+
+``--plain-only`` skips the last four.  Other forms (--form): ``dual`` (the
 same graph's dual, s in {2, 8, 32}); ``batch`` and ``serve`` alone (with
 --autotune, --duration and catalog options); ``copy`` (a plain device copy
 of known size, the calibration run for the FETCH_SIZE / WRITE_SIZE
@@ -63,7 +68,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--form", default="plain",
-                   choices=["plain", "dual", "batch", "serve", "copy", "cpu"])
+                   choices=["plain", "dual", "batch", "serve", "stages", "copy", "cpu"])
     p.add_argument("--plain-only", action="store_true",
                    help="plain form: skip the uniform, batch and serve sub-objects")
     p.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
@@ -579,6 +584,114 @@ def bench_serve(args, catalog, dev):
     }
 
 
+# ----------------------------------------------------------- stages form
+
+def _timed_ms(fn, reps=3):
+    import torch
+
+    ts = []
+    out = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+        if reps > 1:
+            del out
+            out = None
+    return float(np.median(ts)), out
+
+
+def bench_stages(g, dev, variant_scale=0.05, variant_s=(2, 4, 6, 8)):
+    """The rows after L_s on the 1,000,000 x 2,000,000 workload: the s-sweep
+    (count the smallest s, filter the rest) against plain builds, squeezing
+    and components per s, relabel-by-degree both ways, and the variants f0..f4
+    of Table III on the same law at `variant_scale` (the variants without
+    visited skipping make a set intersection per wedge), with the oracle's
+    heuristic algorithm (O2) timed on the host for the same variants."""
+    import torch
+
+    import oracle
+    from paper_2010_11448_amd import gen, sline
+
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    ctx = sline.Context(0)
+    out = {}
+    s_list = list(gen.POWERLAW_S)
+    ctx.build_sweep(rp, col, g.n_vertices, s_list, 0)  # warm
+    t_sweep, _ = _timed_ms(lambda: ctx.build_sweep(rp, col, g.n_vertices, s_list, 0))
+    plain = {}
+    for s in s_list:
+        plain[s], _ = _timed_ms(lambda: ctx.build(rp, col, g.n_vertices, s, 0))
+    torch.cuda.empty_cache()
+    L1 = ctx.build(rp, col, g.n_vertices, 1, 0)
+    t_filter, L2 = _timed_ms(lambda: ctx.filter(L1, 2), reps=1)
+    filt_bytes = 16.0 * len(L1) + 12.0 * len(L2)  # w twice, a and b once; kept pairs written
+    del L1, L2
+    torch.cuda.empty_cache()
+    out["sweep"] = {"s": s_list, "sweep_ms": t_sweep, "plain_ms_sum": sum(plain.values()),
+                    "plain_ms": {str(k): v for k, v in plain.items()},
+                    "sweep_vs_plain": sum(plain.values()) / t_sweep,
+                    "filter_l1_to_l2_ms": t_filter,
+                    "filter_GBps": filt_bytes / 1e6 / t_filter}
+    log(f"stages: sweep {t_sweep:.1f} ms vs plain {sum(plain.values()):.1f} ms")
+    per_s = {}
+    for s in s_list:
+        L = ctx.build(rp, col, g.n_vertices, s, 0)
+        rec = {"pairs": len(L)}
+        if len(L) < (1 << 31) - 1:
+            rec["squeeze_ms"], G = _timed_ms(lambda: ctx.squeeze(L, g.n_edges), reps=1)
+            rec["nodes"] = G["n_nodes"]
+            del G
+        rec["components_ms"], (comp, ncomp) = _timed_ms(lambda: ctx.components(L, g.n_edges),
+                                                        reps=1)
+        rec["components"] = ncomp
+        rec["build_ms"] = plain[s]
+        per_s[str(s)] = rec
+        del L, comp
+        torch.cuda.empty_cache()
+        log(f"stages: s={s} {rec}")
+    out["squeeze_components"] = per_s
+    rel = {}
+    for name, flag in (("asc", sline.SLINE_RELABEL_ASC), ("desc", sline.SLINE_RELABEL_DESC)):
+        rel[name] = {}
+        for s in (2, 4, 8, 16):
+            t, _ = _timed_ms(lambda: ctx.build(rp, col, g.n_vertices, s, 0, flag), reps=2)
+            rel[name][str(s)] = t
+        log(f"stages: relabel {name} {rel[name]}")
+    rel["plain"] = {str(s): plain[s] for s in (2, 4, 8, 16)}
+    out["relabel_ms"] = rel
+    torch.cuda.empty_cache()
+    # variants f0..f4 on a smaller graph of the same law
+    h = gen.powerlaw_1m(scale=variant_scale)
+    hr = torch.from_numpy(h.row_ptr).to(dev)
+    hc = torch.from_numpy(h.col).to(dev)
+    threads = oracle_threads()
+    var = {"workload": h.meta.get("workload"), "n_edges": h.n_edges, "nnz": h.nnz,
+           "s": list(variant_s), "cpu_threads": threads, "gpu_ms": {}, "cpu_o2_ms": {},
+           "intersections": {}}
+    for v in ("f0", "f1", "f2", "f3", "f4"):
+        fl = sline.VARIANT_FLAGS[v]
+        var["gpu_ms"][v] = {}
+        var["cpu_o2_ms"][v] = {}
+        var["intersections"][v] = {}
+        for s in variant_s:
+            ctx.build(hr, hc, h.n_vertices, s, 0, fl)
+            t, _ = _timed_ms(lambda: ctx.build(hr, hc, h.n_vertices, s, 0, fl), reps=2)
+            var["gpu_ms"][v][str(s)] = t
+            t0 = time.perf_counter()
+            _, ost = oracle.alg_h(h.row_ptr, h.col, h.n_edges, h.n_vertices, s,
+                                  variant=oracle.VARIANTS[v], threads=threads, keep=False)
+            var["cpu_o2_ms"][v][str(s)] = (time.perf_counter() - t0) * 1e3
+            var["intersections"][v][str(s)] = ost.intersections
+        log(f"stages: variant {v} gpu {var['gpu_ms'][v]} cpu {var['cpu_o2_ms'][v]}")
+    out["variants"] = var
+    ctx.close()
+    return out
+
+
 METRIC = "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99"
 
 
@@ -611,6 +724,9 @@ def main():
                           "ms_per_step": res["batched_ms_p50"], "config": {"workload": res["workload"]},
                           "batch": res}), flush=True)
         return
+    if args.form == "stages":
+        print(json.dumps({"form": "stages", "stages": bench_stages(g, dev)}), flush=True)
+        return
     if args.form == "serve":
         res = bench_serve(args, catalog, dev)
         print(json.dumps({"metric": METRIC, "value": res["saturation_entries_per_s"],
@@ -630,6 +746,8 @@ def main():
         del batch_h
         log("serving")
         line["serve"] = bench_serve(args, catalog, dev)
+        log("stages after L_s")
+        line["stages"] = bench_stages(g, dev)
     if not args.no_cpu_baseline and not args.spgemm:
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(g, dual, gpu_ms)
