@@ -495,6 +495,7 @@ def bench_serve(args, catalog, dev):
     qs = gen.serving_arrivals(ns, nl, rate=args.rate, duration_s=args.duration)
     srv = sline.Server(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=64,
                        workers=args.workers)
+    srv.set_reuse(REUSE_BYTES, REUSE_MIN_NNZ)
     ids = [srv.register(rp, col, n) for rp, col, n in dgr]
     # warm the server: a few queries, and the largest result of each large
     # graph (maps the device memory its cache will reuse)
@@ -538,14 +539,27 @@ def bench_serve(args, catalog, dev):
     batch_sizes = [infos[i]["batch_size"] for i in range(len(qs))]
     first = min(infos[i]["t_submit_ns"] for i in range(len(qs)))
     last = max(infos[i]["t_done_ns"] for i in range(len(qs)))
-    log("saturation: every query at once")
-    t1 = time.perf_counter()
-    ts = [srv.submit(ids[q.graph_id], q.s, q.dual) for q in qs]
-    while ts:
-        ts = [t for t in ts if srv.poll(t, keep=False) is None]
-        if ts:
-            time.sleep(0.0002)
-    t_sat = time.perf_counter() - t1
+    reuse_arrival = srv.reuse_stats()
+
+    def saturate():
+        t1 = time.perf_counter()
+        ts = [srv.submit(ids[q.graph_id], q.s, q.dual) for q in qs]
+        while ts:
+            ts = [t for t in ts if srv.poll(t, keep=False) is None]
+            if ts:
+                time.sleep(0.0002)
+        return time.perf_counter() - t1
+
+    # saturation: every query at once, first without result reuse, then with
+    # it starting from nothing kept
+    log("saturation without result reuse")
+    srv.set_reuse(0)
+    t_sat_plain_server = saturate()
+    log("saturation with result reuse")
+    srv.set_reuse(REUSE_BYTES, REUSE_MIN_NNZ)
+    r0 = srv.reuse_stats()
+    t_sat = saturate()
+    r1 = srv.reuse_stats()
     srv.close()
     log("plain calls, one per query")
     torch.cuda.empty_cache()
@@ -564,6 +578,10 @@ def bench_serve(args, catalog, dev):
     t_plain = time.perf_counter() - t2
     ctx.close()
     large = [lat[i] for i, q in enumerate(qs) if q.graph_id >= ns]
+    slowest = sorted(range(len(qs)), key=lambda i: -lat[i])[:8]
+    slow = [{"ms": lat[i], "large": qs[i].graph_id >= ns, "s": qs[i].s, "dual": qs[i].dual,
+             "batch": infos[i]["batch_size"],
+             "wait_ms": (infos[i]["t_start_ns"] - infos[i]["t_submit_ns"]) / 1e6} for i in slowest]
     small = [lat[i] for i, q in enumerate(qs) if q.graph_id < ns]
     return {
         "workload": f"serving_poisson{args.rate:.0f}_{args.duration:.0f}s",
@@ -581,6 +599,13 @@ def bench_serve(args, catalog, dev):
         "plain_s": t_plain, "plain_large_s": t_plain_large,
         "plain_queries_per_s": len(qs) / t_plain,
         "served_vs_plain": t_plain / t_sat,
+        "saturation_no_reuse_s": t_sat_plain_server,
+        "served_vs_plain_no_reuse": t_plain / t_sat_plain_server,
+        "slowest": slow,
+        "reuse": {"cache_bytes": REUSE_BYTES, "min_nnz": REUSE_MIN_NNZ,
+                  "arrival_run_reused": reuse_arrival["reused"],
+                  "saturation_reused": r1["reused"] - r0["reused"],
+                  "saturation_kept": r1["kept"] - r0["kept"]},
     }
 
 
@@ -693,6 +718,9 @@ def bench_stages(g, dev, variant_scale=0.05, variant_s=(2, 4, 6, 8)):
 
 
 METRIC = "s-line graph build: incidence entries/s, % HBM peak; batched vs plain; p50/p99"
+# serving: device bytes of kept results that answer later queries by a filter
+REUSE_BYTES = 32 << 30
+REUSE_MIN_NNZ = 1 << 20
 
 
 def main():

@@ -391,6 +391,23 @@ sline_status sline_server_poll(sline_server *srv, int64_t ticket, sline_edges *o
  * it any more, and zero the struct. */
 sline_status sline_server_release(sline_server *srv, sline_edges *out);
 
+/* Result reuse.  L_s keeps the pairs of L_s' (s' <= s) with w >= s, with
+ * the same weights (Sec. III).  The server keeps, per (graph, side), a copy
+ * of the result of the smallest s computed so far, for graphs of at least
+ * min_nnz incidences, within cache_bytes of device memory beside the
+ * budget (one result at most half of it; least recently used first out; a
+ * build that runs out of device memory drops them and is tried again).  A later query of
+ * that graph and side with s >= the kept s is answered by sline_filter from
+ * it instead of a build; the answer is the same.  cache_bytes = 0 turns
+ * reuse off and drops what is kept.  Defaults: a quarter of the budget (at
+ * most 32 GiB), min_nnz = 2^20. */
+sline_status sline_server_set_reuse(sline_server *srv, int64_t cache_bytes, int64_t min_nnz);
+
+/* Queries answered by reuse, results kept so far, and bytes kept now (any
+ * pointer may be NULL). */
+sline_status sline_server_reuse_stats(sline_server *srv, int64_t *reused, int64_t *kept,
+                                      int64_t *kept_bytes);
+
 /* Queries waiting and batches running (either pointer may be NULL). */
 sline_status sline_server_pending(sline_server *srv, int64_t *queued, int32_t *running);
 

@@ -240,6 +240,7 @@ struct Query {
     int64_t ticket = 0;
     int32_t graph = 0, s = 1, dual = 0;
     int64_t est = 0;
+    bool reused = false;  // answered by filtering a kept result
     sline_query_info info{};
     sline_edges out{};
     bool done = false;
@@ -271,6 +272,30 @@ struct sline_server {
     DeviceCache cache;                            // device memory of every worker
     bool log = false;                             // SLINE_SERVER_LOG set: one line per batch
     std::string last_error;
+    // Result reuse.  L_s keeps the pairs of L_s' (s' <= s) with w >= s, with
+    // the same weights (Sec. III), so a kept L_s' answers every later query
+    // of the same graph and side with s >= s' by a filter instead of a
+    // build.  Per (graph, side) the result of the smallest s computed so far
+    // is kept (a copy in the device cache), within reuse_cap bytes, least
+    // recently used first out; an entry being filtered from is never freed.
+    struct Kept {
+        int32_t s = 0;
+        sline_edges e{};
+        int64_t bytes = 0;
+        int64_t last = 0;
+        int32_t users = 0;
+    };
+    std::map<std::pair<int32_t, int32_t>, Kept> kept;
+    // result arrays shared by a client and a kept entry: owners beyond one
+    std::unordered_map<void *, int32_t> extra_refs;
+    // (graph, side) being built by a running batch: the smallest s; a query
+    // of the same key with s at least that waits for the result to be kept
+    std::map<std::pair<int32_t, int32_t>, int32_t> building;
+    int64_t kept_bytes = 0;
+    int64_t reuse_cap = 0;      // bytes the kept results may hold (0: no reuse)
+    int64_t reuse_min_nnz = 0;  // graphs with fewer incidences are not kept
+    int64_t use_clock = 0;
+    int64_t n_reused = 0, n_kept = 0;  // queries answered by a filter, results kept
 };
 
 namespace {
@@ -278,6 +303,78 @@ namespace {
 // Device bytes a handed-over result holds until it is released.
 int64_t result_bytes(const sline_edges &e) {
     return (int64_t)sizeof(int32_t) * e.n_pairs * (e.w ? 3 : 2);
+}
+
+int64_t kept_result_bytes(const sline_edges &e) {
+    return (int64_t)sizeof(int32_t) * e.n_pairs * 3;
+}
+
+// One owner of a result array lets go (caller holds S->mu): the array is
+// freed with its last owner.
+void unref(sline_server *S, void *p) {
+    if (!p) return;
+    auto it = S->extra_refs.find(p);
+    if (it != S->extra_refs.end()) {
+        if (--it->second > 0) return;
+        S->extra_refs.erase(it);
+        return;
+    }
+    S->cache.release(p, nullptr);
+}
+
+void add_ref(sline_server *S, void *p) {
+    if (p) S->extra_refs[p] += 1;
+}
+
+// Let go of the arrays of a kept result (caller holds S->mu; the entry has
+// no users).
+void drop_kept(sline_server *S, sline_server::Kept &k) {
+    unref(S, k.e.a);
+    unref(S, k.e.b);
+    unref(S, k.e.w);
+    S->kept_bytes -= k.bytes;
+    k = sline_server::Kept{};
+}
+
+// Least recently used kept results out until they fit `cap` (caller holds
+// S->mu); entries in use stay.
+void evict_kept(sline_server *S, int64_t cap) {
+    while (S->kept_bytes > cap) {
+        auto victim = S->kept.end();
+        for (auto it = S->kept.begin(); it != S->kept.end(); ++it)
+            if (it->second.users == 0 && (victim == S->kept.end() || it->second.last < victim->second.last))
+                victim = it;
+        if (victim == S->kept.end()) return;
+        drop_kept(S, victim->second);
+        S->kept.erase(victim);
+    }
+}
+
+// Keep a computed result (its arrays shared with the client, no copy) if it
+// is the smallest s of its graph and side so far and fits the reuse budget
+// (caller holds S->mu).
+void keep_result(sline_server *S, int32_t graph, int32_t dual, int32_t s, const sline_edges &res) {
+    const int64_t bytes = kept_result_bytes(res);
+    if (S->reuse_cap <= 0 || bytes > S->reuse_cap / 2 || !res.w || res.n_pairs == 0 ||
+        S->graphs[graph].nnz < S->reuse_min_nnz)
+        return;
+    auto it = S->kept.find({graph, dual});
+    if (it != S->kept.end()) {
+        if (it->second.s <= s || it->second.users > 0) return;
+        drop_kept(S, it->second);
+    }
+    sline_server::Kept &k = S->kept[{graph, dual}];
+    k.s = s;
+    k.e = sline_edges{res.n_pairs, 0, res.a, res.b, res.w};
+    k.bytes = bytes;
+    k.last = ++S->use_clock;
+    k.users = 0;
+    add_ref(S, res.a);
+    add_ref(S, res.b);
+    add_ref(S, res.w);
+    S->kept_bytes += bytes;
+    S->n_kept += 1;
+    evict_kept(S, S->reuse_cap);
 }
 
 int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual) {
@@ -290,7 +387,10 @@ void worker_loop(sline_server *S, int wi) {
     sline_server::Worker &W = S->workers[wi];
     (void)hipSetDevice(S->device);
     for (;;) {
-        std::vector<int64_t> batch;
+        std::vector<int64_t> batch;   // queries counted by one batched build
+        std::vector<int64_t> reuse;   // queries filtered from a kept result
+        std::vector<sline_edges> from;
+        std::vector<std::pair<int32_t, int32_t>> from_key;
         int64_t est = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
@@ -298,26 +398,60 @@ void worker_loop(sline_server *S, int wi) {
                 if (S->stop) return;
                 // admit in arrival order while the batch and the budget allow;
                 // a query larger than the budget runs alone when nothing else does
-                while (!S->queue.empty() && (int32_t)batch.size() < S->max_batch) {
-                    Query &q = S->queries[S->queue.front()];
+                for (auto qi = S->queue.begin();
+                     qi != S->queue.end() && (int32_t)(batch.size() + reuse.size()) < S->max_batch;) {
+                    Query &q = S->queries[*qi];
+                    const std::pair<int32_t, int32_t> key{q.graph, q.dual};
+                    auto kt = S->kept.find(key);
+                    const bool can_reuse = kt != S->kept.end() && kt->second.s <= q.s;
+                    if (!can_reuse && S->reuse_cap > 0) {
+                        // a running build of the same graph and side with a
+                        // smaller s will answer this query once it is kept
+                        auto bt = S->building.find(key);
+                        if (bt != S->building.end() && bt->second <= q.s) {
+                            ++qi;
+                            continue;
+                        }
+                    }
+                    // a filtered result is at most the kept one
+                    const int64_t qe =
+                        can_reuse ? kt->second.bytes + ((int64_t)1 << 20) : q.est;
                     // results the client has not released count against the
-                    // budget too (so a slow client holds back admission)
-                    const bool alone = S->in_flight == 0 && batch.empty();
-                    if (!alone && S->in_flight + S->held + est + q.est > S->budget) break;
-                    est += q.est;
-                    batch.push_back(q.ticket);
-                    S->queue.pop_front();
+                    // budget too (so a slow client holds back admission); kept
+                    // results live beside the budget, within their own cap,
+                    // and give way when a build runs out of device memory
+                    const bool alone = S->in_flight == 0 && batch.empty() && reuse.empty();
+                    const bool fits = S->in_flight + S->held + est + qe <= S->budget;
+                    if (!alone && !fits) break;
+                    // a build above the whole budget runs alone, with all the
+                    // device memory the kept results would hold
+                    if (!fits && !can_reuse) evict_kept(S, 0);
+                    est += qe;
+                    if (can_reuse) {
+                        kt->second.users += 1;
+                        kt->second.last = ++S->use_clock;
+                        q.reused = true;
+                        reuse.push_back(q.ticket);
+                        from.push_back(kt->second.e);
+                        from_key.push_back(kt->first);
+                    } else {
+                        batch.push_back(q.ticket);
+                        auto bt = S->building.find(key);
+                        if (bt == S->building.end() || bt->second > q.s) S->building[key] = q.s;
+                    }
+                    qi = S->queue.erase(qi);
                 }
-                if (!batch.empty()) break;
+                if (!batch.empty() || !reuse.empty()) break;
                 S->cv.wait(lk);
             }
             S->in_flight += est;
             S->running += 1;
         }
         const int32_t G = (int32_t)batch.size();
+        const int32_t R = (int32_t)reuse.size();
         std::vector<sline_csr> Hs(G);
-        std::vector<int32_t> ss(G), ds(G);
-        std::vector<sline_edges> outs(G);
+        std::vector<int32_t> ss(G), ds(G), gs(G), rs(R);
+        std::vector<sline_edges> outs(G), routs(R);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             const int64_t t = now_ns();
@@ -326,12 +460,35 @@ void worker_loop(sline_server *S, int wi) {
                 Hs[g] = S->graphs[q.graph].H;
                 ss[g] = q.s;
                 ds[g] = q.dual;
+                gs[g] = q.graph;
                 outs[g] = sline_edges{};
                 q.info.t_start_ns = t;
                 q.info.batch_size = G;
                 q.worker = wi;
             }
+            for (int32_t r = 0; r < R; ++r) {
+                Query &q = S->queries[reuse[r]];
+                rs[r] = q.s;
+                routs[r] = sline_edges{};
+                q.info.t_start_ns = t;
+                q.info.batch_size = 1;
+                q.worker = wi;
+            }
         }
+        // queries answered from kept results: one filter each
+        std::vector<sline_status> rst(R, SLINE_OK);
+        for (int32_t r = 0; r < R; ++r) rst[r] = sline_filter(W.ctx, &from[r], rs[r], 0, &routs[r]);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (int32_t r = 0; r < R; ++r) {
+                auto kt = S->kept.find(from_key[r]);
+                if (kt != S->kept.end()) kt->second.users -= 1;
+            }
+            S->n_reused += R;
+        }
+        std::string rerr;
+        for (int32_t r = 0; r < R; ++r)
+            if (rst[r] != SLINE_OK) rerr = sline_last_error(W.ctx);
         int64_t c0[5] = {0, 0, 0, 0, 0};
         if (S->log) {
             std::lock_guard<std::mutex> lk(S->cache.mu);
@@ -343,8 +500,23 @@ void worker_loop(sline_server *S, int wi) {
         }
         const int64_t t_run = now_ns();
         const uint32_t flags = S->log ? SLINE_PROFILE : 0;
-        sline_status st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), flags,
-                                            outs.data());
+        sline_status st = G > 0 ? sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), flags,
+                                                    outs.data())
+                                : SLINE_OK;
+        if (st == SLINE_ENOMEM) {
+            // kept results give way to builds: drop those not being read, retry
+            bool dropped = false;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                const int64_t before = S->kept_bytes;
+                evict_kept(S, 0);
+                dropped = S->kept_bytes < before;
+            }
+            if (dropped) {
+                for (auto &o : outs) o = sline_edges{};
+                st = sline_build_batch(W.ctx, G, Hs.data(), ss.data(), ds.data(), flags, outs.data());
+            }
+        }
         // per query: the batch's status, or its own when the batch ran apart
         std::vector<sline_status> qst(G, st);
         const bool apart = (st == SLINE_ENOMEM || st == SLINE_EINVAL) && G > 1;
@@ -393,6 +565,13 @@ void worker_loop(sline_server *S, int wi) {
         std::string err = st == SLINE_OK ? std::string() : std::string(sline_last_error(W.ctx));
         {
             std::lock_guard<std::mutex> lk(S->mu);
+            // keep the results that can answer later queries of their graph
+            // and side; the builds of this batch are no longer running
+            for (int32_t g = 0; g < G; ++g) {
+                if (qst[g] == SLINE_OK) keep_result(S, gs[g], ds[g], ss[g], outs[g]);
+                auto bt = S->building.find({gs[g], ds[g]});
+                if (bt != S->building.end() && bt->second == ss[g]) S->building.erase(bt);
+            }
             for (int32_t g = 0; g < G; ++g) {
                 Query &q = S->queries[batch[g]];
                 q.info.status = qst[g];
@@ -404,7 +583,19 @@ void worker_loop(sline_server *S, int wi) {
                 }
                 q.done = true;
             }
+            for (int32_t r = 0; r < R; ++r) {
+                Query &q = S->queries[reuse[r]];
+                q.info.status = rst[r];
+                q.info.t_done_ns = t_done;
+                if (rst[r] == SLINE_OK) {
+                    q.out = routs[r];
+                    q.info.n_pairs = routs[r].n_pairs;
+                    S->held += result_bytes(routs[r]);
+                }
+                q.done = true;
+            }
             if (st != SLINE_OK) S->last_error = err;
+            else if (!rerr.empty()) S->last_error = rerr;
             S->in_flight -= est;
             S->running -= 1;
         }
@@ -412,11 +603,12 @@ void worker_loop(sline_server *S, int wi) {
     }
 }
 
-// Results live in the server's cache; a release returns them to it.
+// Results live in the server's cache; a release returns them to it unless a
+// kept entry still shares them (caller holds S->mu).
 void free_arrays(sline_server *S, const sline_edges &e) {
-    S->cache.release(e.a, nullptr);
-    S->cache.release(e.b, nullptr);
-    S->cache.release(e.w, nullptr);
+    unref(S, e.a);
+    unref(S, e.b);
+    unref(S, e.w);
 }
 
 }  // namespace
@@ -443,7 +635,11 @@ sline_status sline_server_create(sline_server **srv, int device, int64_t hbm_bud
     al.free = cache_free;
     al.user = &S->cache;
     S->log = getenv("SLINE_SERVER_LOG") != nullptr;
-    S->cache.reserve((size_t)hbm_budget_bytes);
+    S->reuse_cap = std::min<int64_t>(hbm_budget_bytes / 4, (int64_t)32 << 30);
+    S->reuse_min_nnz = (int64_t)1 << 20;
+    // the budget and the kept results, mapped once (fresh device memory costs
+    // far more than a build)
+    S->cache.reserve((size_t)(hbm_budget_bytes + S->reuse_cap));
     S->workers.resize(n_workers);
     for (auto &W : S->workers) {
         if (hipStreamCreateWithFlags(&W.stream, hipStreamNonBlocking) != hipSuccess) {
@@ -554,14 +750,44 @@ sline_status sline_server_poll(sline_server *S, int64_t ticket, sline_edges *out
 
 sline_status sline_server_release(sline_server *S, sline_edges *out) {
     if (!S || !out) return SLINE_EINVAL;
-    if (out->a || out->b) {
+    {
         std::lock_guard<std::mutex> lk(S->mu);
-        S->held = std::max<int64_t>(0, S->held - result_bytes(*out));
+        if (out->a || out->b) S->held = std::max<int64_t>(0, S->held - result_bytes(*out));
+        free_arrays(S, *out);
     }
-    free_arrays(S, *out);
     S->cv.notify_all();  // admission may have waited on the released memory
     out->a = out->b = out->w = nullptr;
     out->n_pairs = 0;
+    return SLINE_OK;
+}
+
+sline_status sline_server_set_reuse(sline_server *S, int64_t cache_bytes, int64_t min_nnz) {
+    if (!S || cache_bytes < 0 || min_nnz < 0) return SLINE_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->reuse_cap = cache_bytes;
+        S->reuse_min_nnz = min_nnz;
+        evict_kept(S, cache_bytes);
+    }
+    // map room for the budget and the kept results up front (if the device
+    // has it to spare)
+    size_t have = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->cache.mu);
+        have = S->cache.total;
+    }
+    const size_t want = (size_t)(S->budget + cache_bytes);
+    if (have < want) S->cache.reserve(want - have);
+    return SLINE_OK;
+}
+
+sline_status sline_server_reuse_stats(sline_server *S, int64_t *reused, int64_t *kept,
+                                      int64_t *kept_bytes) {
+    if (!S) return SLINE_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (reused) *reused = S->n_reused;
+    if (kept) *kept = S->n_kept;
+    if (kept_bytes) *kept_bytes = S->kept_bytes;
     return SLINE_OK;
 }
 
@@ -586,8 +812,13 @@ void sline_server_destroy(sline_server *S) {
     S->cv.notify_all();
     for (auto &W : S->workers)
         if (W.th.joinable()) W.th.join();
-    for (auto &kv : S->queries)
-        if (kv.second.done) free_arrays(S, kv.second.out);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto &kv : S->queries)
+            if (kv.second.done) free_arrays(S, kv.second.out);
+        for (auto &kv : S->kept) free_arrays(S, kv.second.e);
+        S->kept.clear();
+    }
     for (auto &W : S->workers) {
         if (W.ctx) sline_destroy(W.ctx);
         if (W.stream) (void)hipStreamDestroy(W.stream);

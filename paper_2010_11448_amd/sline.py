@@ -152,6 +152,10 @@ SIGNATURES = {
     "sline_server_pending": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int32)]),
     "sline_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "sline_server_set_reuse": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
+    "sline_server_reuse_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                                  ctypes.POINTER(ctypes.c_int64),
+                                                  ctypes.POINTER(ctypes.c_int64)]),
     "sline_server_destroy": (None, [ctypes.c_void_p]),
     "sline_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
@@ -568,6 +572,17 @@ class Server:
         if st != SLINE_OK:
             raise SlineError(st, "sline_server_submit failed")
         return int(t.value)
+
+    def set_reuse(self, cache_bytes: int, min_nnz: int = 0) -> None:
+        """Result reuse (sline_server_set_reuse); cache_bytes = 0 turns it off."""
+        st = load().sline_server_set_reuse(self.srv, int(cache_bytes), int(min_nnz))
+        if st != SLINE_OK:
+            raise SlineError(st, "sline_server_set_reuse failed")
+
+    def reuse_stats(self) -> dict:
+        r, k, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        load().sline_server_reuse_stats(self.srv, ctypes.byref(r), ctypes.byref(k), ctypes.byref(b))
+        return {"reused": int(r.value), "kept": int(k.value), "kept_bytes": int(b.value)}
 
     def pending(self) -> tuple[int, int]:
         q, r = ctypes.c_int64(), ctypes.c_int32()

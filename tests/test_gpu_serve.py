@@ -49,13 +49,17 @@ def _drain(srv, tickets, timeout_s=120.0):
     return done
 
 
-@pytest.mark.parametrize("workers,budget", [(2, 64 << 30), (1, 1 << 20)])
-def test_mixed_queries_equal_alone(dev, workers, budget):
+@pytest.mark.parametrize("workers,budget,reuse", [(2, 64 << 30, False), (1, 1 << 20, False),
+                                                  (2, 64 << 30, True), (3, 8 << 30, True)])
+def test_mixed_queries_equal_alone(dev, workers, budget, reuse):
     from paper_2010_11448_amd import sline
 
     graphs = _catalog()
     dg = [to_device(h, dev) for h in graphs]
     srv = sline.Server(0, hbm_budget_bytes=budget, max_batch=16, workers=workers)
+    # reuse on every graph (kept results answer later queries by a filter),
+    # or none at all
+    srv.set_reuse(1 << 30 if reuse else 0, 0)
     ctx = sline.Context(0)
     try:
         ids = [srv.register(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)]
@@ -68,11 +72,15 @@ def test_mixed_queries_equal_alone(dev, workers, budget):
         tickets = [srv.submit(ids[g], s, d) for g, s, d in queries]
         done = _drain(srv, tickets)
         sizes = [done[t][1]["batch_size"] for t in tickets]
-        if budget >= 1 << 30:
+        if budget >= 1 << 30 and not reuse:
             assert max(sizes) > 1, "queries submitted together should share batches"
-        else:
+        elif budget < 1 << 30:
             # every estimate exceeds a 1 MiB budget: each query runs alone
             assert max(sizes) == 1
+        if reuse:
+            assert srv.reuse_stats()["reused"] > 0, "no query was answered from a kept result"
+        else:
+            assert srv.reuse_stats()["reused"] == 0
         for (g, s, d), t in zip(queries, tickets):
             L, info = done[t]
             assert info["status"] == 0 and info["n_pairs"] == len(L)
