@@ -454,9 +454,30 @@ def bench_batch(args, graphs_h, dev, steps, warmup):
         torch.cuda.synchronize()
         tp.append(time.perf_counter() - t0)
         log(f"plain step {i + 1}/{steps} {tp[-1] * 1e3:.1f} ms")
+    # the same batch as a plan: sized once, then replayed as one graph launch
+    # with the results left in the plan's arrays
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sline.BatchPlan(ctx, graphs, s_list, dual)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    plan_bytes, plan_tasks, plan_pairs = plan.info()
+    for _ in range(max(warmup, 1)):
+        plan.run_raw()
+    tr = []
+    for i in range(steps):
+        t0 = time.perf_counter()
+        rc = plan.run_raw()
+        tr.append(time.perf_counter() - t0)
+        if rc != sline.SLINE_OK:
+            raise sline.SlineError(rc, sline.sline_last_error(ctx.ctx))
+        log(f"plan replay {i + 1}/{steps} {tr[-1] * 1e3:.1f} ms")
+    plan_pairs_run = int(ctx.stats()["n_pairs"])
+    plan.close()
     ctx.close()
     t_batch = sum(tb) / len(tb)
     t_plain = sum(tp) / len(tp)
+    t_plan = sum(tr) / len(tr)
     b = 12.0 * st["heavy_nnz"] + 4.0 * st["heavy_wedges"] + 8.0 * st["heavy_pairs"]
     ach = b / 1e9 / (st["ms_tasks"] / 1e3) if st["ms_tasks"] > 0 else 0.0
     return {
@@ -472,6 +493,12 @@ def bench_batch(args, graphs_h, dev, steps, warmup):
         "batched_stage_ms": {k: st[k] for k in ("ms_transpose", "ms_prepare", "ms_count",
                                                 "ms_scan", "ms_fill", "ms_tasks")},
         "task_kernel_GBps": ach,
+        "plan": {"replay_ms_p50": pct([x * 1e3 for x in tr], 50),
+                 "replay_ms_p99": pct([x * 1e3 for x in tr], 99),
+                 "replay_vs_batched": t_batch / t_plan, "replay_vs_plain": t_plain / t_plan,
+                 "create_ms": t_create * 1e3, "device_bytes": plan_bytes,
+                 "task_capacity": plan_tasks, "pair_capacity": plan_pairs,
+                 "pairs": plan_pairs_run},
     }
 
 

@@ -325,6 +325,54 @@ sline_status sline_build_batch(sline_ctx *ctx, int32_t n_graphs, const sline_csr
                                const int32_t *s, const int32_t *dual, uint32_t flags,
                                sline_edges *outs);
 
+/* ---------------------------------------------------------- batch plans
+ * A batch (as in sline_build_batch) sized once and then replayed as one HIP
+ * graph launch: no size read-back and no allocation between its ~40 kernels,
+ * one read-back of the per-graph pair counts at the end.  Not a step of the
+ * paper: it is the launch form of repeated batched builds (the same graphs,
+ * rebuilt after their member lists change in place, or swept to larger s).
+ *
+ * sline_batch_plan_create checks the graphs, runs the batch's counting once
+ * to learn its sizes, then allocates every buffer of the pipeline through the
+ * context's allocator -- the combined item lists, the transposes, the task
+ * arrays (exactly the tasks counted), the staging pool (W_s / s_min pairs,
+ * capped by the tuning's stage_max_bytes) and the result arrays (exactly the
+ * pairs counted) -- and captures the pipeline on a stream of its own into a
+ * graph.  It uses the context's tuning as it is at creation.  The graphs'
+ * arrays are the caller's: they must stay allocated, with the same row_ptr[m],
+ * n_edges and n_vertices, for the plan's lifetime; their contents may change
+ * between runs.
+ *
+ * sline_batch_plan_run launches the graph on the context's stream and waits
+ * for it.  s (nullable: the planned values) gives each graph's s for this
+ * run; each must be >= the planned s of its graph (larger s only shrinks the
+ * work and the result, Sec. III).  outs[g] receives graph g's L_s in the
+ * plan's own result arrays: a, b, w (w null with SLINE_NO_WEIGHTS) point into
+ * them, n_pairs is set and capacity is 0.  They stay valid until the next run
+ * or sline_batch_plan_destroy; never pass them to sline_edges_free.
+ * Results equal sline_build_batch's for the same graphs, s and flags.
+ * Errors (outs untouched unless SLINE_OK):
+ *   SLINE_EINVAL     bad arguments; a graph breaks the rules of sline_csr, or
+ *                    its row_ptr[0] / row_ptr[m] changed since the plan was made;
+ *                    a run's s below the planned s; flags other than
+ *                    SLINE_NO_WEIGHTS.
+ *   SLINE_ECAPACITY  the run needs more tasks or pairs than the plan holds
+ *                    (changed contents); make a new plan.
+ *   SLINE_ENOMEM     allocation failed (create only).
+ *   SLINE_EDEVICE    a HIP call failed (graph capture included).
+ * A plan belongs to its context: use it from one thread at a time with the
+ * context's other calls, and destroy it before the context. */
+typedef struct sline_batch_plan sline_batch_plan;
+
+sline_status sline_batch_plan_create(sline_ctx *ctx, int32_t n_graphs, const sline_csr *Hs,
+                                     const int32_t *s, const int32_t *dual, uint32_t flags,
+                                     sline_batch_plan **plan);
+sline_status sline_batch_plan_run(sline_batch_plan *plan, const int32_t *s, sline_edges *outs);
+/* Device bytes the plan holds, and its task and pair capacities. */
+sline_status sline_batch_plan_info(const sline_batch_plan *plan, int64_t *device_bytes,
+                                   int64_t *task_capacity, int64_t *pair_capacity);
+void sline_batch_plan_destroy(sline_batch_plan *plan);
+
 /* ------------------------------------------------------------- serving
  * A query loop over resident hypergraphs.  Registered graphs stay where the
  * caller keeps them (device CSR arrays that must outlive the server).

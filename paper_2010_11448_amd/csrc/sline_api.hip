@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1077,6 +1078,126 @@ sline_status batch_split(sline_ctx *c, int32_t G, sline_edges *outs) {
     return SLINE_OK;
 }
 
+// Combined sizes of a batch and the bases of every graph in them (its first
+// combined item and member; for dual graphs, its first row and entry in XD,
+// the row concatenation of the dual graphs, and its first row of XD^T).
+struct BatchBases {
+    std::vector<int64_t> ibase, dbase;  // ibase: G + 1 entries; dbase: GD + 1
+    std::vector<int32_t> dual_ids;      // the dual graphs, in order
+    int64_t NI = 0, MT = 0, ZT = 0, E = 0, ZD = 0, VD = 0;
+    int32_t GD() const { return (int32_t)dual_ids.size(); }
+};
+
+// Sets every descriptor's nnz and bases from the graphs' nnz.  SLINE_EINVAL
+// (error set) for a bad nnz, a missing col_idx, or combined counts of 2^31 or
+// more.
+sline_status batch_bases(sline_ctx *c, std::vector<BatchGraph> &gr, const std::vector<int64_t> &nnz,
+                         BatchBases &B) {
+    const int32_t G = (int32_t)gr.size();
+    B = BatchBases{};
+    B.ibase.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+        BatchGraph &d = gr[g];
+        if (nnz[g] < 0 || (nnz[g] > 0 && (!d.col || d.n == 0))) {
+            set_err(c, "graph %s: bad nnz or missing col_idx", std::to_string(g).c_str());
+            return SLINE_EINVAL;
+        }
+        d.nnz = nnz[g];
+        d.ibase = B.NI;
+        d.mbase = B.MT;
+        B.ibase[g] = B.NI;
+        B.NI += d.dual ? d.n : d.m;
+        B.MT += d.dual ? d.m : d.n;
+        B.ZT += nnz[g];
+        if (d.dual) {
+            d.dbase = B.E;
+            d.dzbase = B.ZD;
+            d.vdbase = B.VD;
+            B.dual_ids.push_back(g);
+            B.dbase.push_back(B.E);
+            B.E += d.m;
+            B.ZD += nnz[g];
+            B.VD += d.n;
+        }
+    }
+    B.ibase[G] = B.NI;
+    B.dbase.push_back(B.E);
+    if (B.NI >= INT32_MAX || B.MT >= INT32_MAX || B.ZT >= INT32_MAX) {
+        set_err(c, "batch too large: combined items, members and incidences must stay below 2^31");
+        return SLINE_EINVAL;
+    }
+    return SLINE_OK;
+}
+
+// Arrays of the combine stage: XD and its transpose, then the combined item
+// CSR with every item's s and graph end.
+struct Combine {
+    Layout X{};
+    int32_t *len = nullptr, *ptrC = nullptr, *memC = nullptr, *s_item = nullptr, *iend = nullptr;
+};
+
+Combine plan_combine(Arena &A, const BatchBases &B) {
+    Combine K;
+    K.X.rowid = A.take<int32_t>(B.ZD);
+    K.X.colT = A.take<int32_t>(B.ZD);
+    K.X.ptrT = A.take<int32_t>(B.VD + 1);
+    K.X.rsK0 = A.take<int32_t>(B.ZD);
+    K.X.rsK1 = A.take<int32_t>(B.ZD);
+    K.X.rsV0 = A.take<int32_t>(B.ZD);
+    K.X.rsV1 = A.take<int32_t>(B.ZD);
+    K.X.rsHist = A.take<int32_t>(16 * transpose_tiles(B.ZD) + 1);
+    K.X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>({B.VD, B.NI, B.ZD}) + 1));
+    K.len = A.take<int32_t>(B.NI);
+    K.ptrC = A.take<int32_t>(B.NI + 1);
+    K.memC = A.take<int32_t>(B.ZT);
+    K.s_item = A.take<int32_t>(B.NI);
+    K.iend = A.take<int32_t>(B.NI);
+    K.X.xcol = A.take<int32_t>(B.ZD);
+    return K;
+}
+
+// Device copies of the descriptors and bases the combine stage reads.
+struct BatchDev {
+    const BatchGraph *gr;
+    const int64_t *ibase, *dbase;
+    const int32_t *dual_ids;
+    int32_t *zb;   // G + 1 entries
+    int32_t *err;  // CSR rule violations (kErr* bits)
+};
+
+// Enqueue the combine stage on `st`: the dual graphs' rows concatenated and
+// transposed, then every combined item's list, s and graph end, with the
+// checks of every caller CSR (bits in D.err).
+void enqueue_combine(sline_ctx *c, hipStream_t st, int32_t G, const BatchBases &B,
+                     const BatchDev &D, const Combine &K) {
+    const Layout &X = K.X;
+    hip_check(c, launch_fill_i32(st, X.xcol, B.ZD, 0), "zero dual columns");
+    hip_check(c, launch_fill_i32(st, X.rowid, B.ZD, 0), "zero dual rows");
+    if (B.GD() > 0 && B.E > 0) {
+        hip_check(c, launch_batch_concat(st, D.gr, D.dual_ids, D.dbase, B.GD(), B.E, X.xcol, X.rowid,
+                                         D.err),
+                  "dual rows");
+        if (B.ZD > 0) {
+            int32_t *const rk[2] = {X.rsK0, X.rsK1};
+            int32_t *const rv[2] = {X.rsV0, X.rsV1};
+            hip_check(c, launch_transpose(st, X.xcol, B.ZD, (int32_t)B.VD, X.rowid, rk, rv, X.rsHist,
+                                          X.part32, X.ptrT, X.colT, nullptr, nullptr),
+                      "dual transpose");
+        } else {
+            hip_check(c, launch_fill_i32(st, X.ptrT, B.VD + 1, 0), "empty transpose");
+        }
+    } else if (B.VD > 0) {
+        hip_check(c, launch_fill_i32(st, X.ptrT, B.VD + 1, 0), "empty transpose");
+    }
+    hip_check(c, launch_batch_len(st, D.gr, D.ibase, G, B.NI, X.ptrT, K.len, K.s_item, K.iend,
+                                  D.err),
+              "item lengths");
+    hip_check(c, launch_scan_i32(st, K.len, B.NI, K.ptrC, X.part32), "item scan");
+    hip_check(c, launch_batch_rows(st, D.gr, D.ibase, G, B.ZT, X.ptrT, X.colT, K.ptrC, D.zb,
+                                   K.memC, D.err),
+              "item rows");
+}
+
 sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int32_t *s,
                         const int32_t *dual, uint32_t flags, sline_edges *outs) {
     if (flags & kBuildOnlyFlags) {
@@ -1156,78 +1277,29 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         return SLINE_EINVAL;
     }
     // 2. bases on the host
-    std::vector<int64_t> ibase(G + 1), dbase;
-    std::vector<int32_t> dual_ids;
-    int64_t NI = 0, MT = 0, ZT = 0, E = 0, ZD = 0, VD = 0;
-    for (int32_t g = 0; g < G; ++g) {
-        BatchGraph &d = gr[g];
-        if (nnz[g] < 0 || (nnz[g] > 0 && (!d.col || d.n == 0))) {
-            set_err(c, "graph %s: bad nnz or missing col_idx", std::to_string(g).c_str());
-            drop_batch_pending(c);
-            return SLINE_EINVAL;
-        }
-        d.nnz = nnz[g];
-        d.ibase = NI;
-        d.mbase = MT;
-        ibase[g] = NI;
-        NI += d.dual ? d.n : d.m;
-        MT += d.dual ? d.m : d.n;
-        ZT += nnz[g];
-        if (d.dual) {
-            d.dbase = E;
-            d.dzbase = ZD;
-            d.vdbase = VD;
-            dual_ids.push_back(g);
-            dbase.push_back(E);
-            E += d.m;
-            ZD += nnz[g];
-            VD += d.n;
-        }
-    }
-    ibase[G] = NI;
-    dbase.push_back(E);
-    if (NI >= INT32_MAX || MT >= INT32_MAX || ZT >= INT32_MAX) {
-        set_err(c, "batch too large: combined items, members and incidences must stay below 2^31");
+    BatchBases B;
+    if (batch_bases(c, gr, nnz, B) != SLINE_OK) {
         drop_batch_pending(c);
         return SLINE_EINVAL;
     }
-    const int32_t GD = (int32_t)dual_ids.size();
+    const int64_t NI = B.NI, MT = B.MT;
+    const int32_t GD = B.GD();
     hip_check(c, hipMemcpyAsync(d_gr, gr.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, st),
               "upload graphs");
-    hip_check(c, hipMemcpyAsync(P.ibase_dev, ibase.data(), sizeof(int64_t) * (G + 1),
+    hip_check(c, hipMemcpyAsync(P.ibase_dev, B.ibase.data(), sizeof(int64_t) * (G + 1),
                                 hipMemcpyHostToDevice, st),
               "upload item bases");
     if (GD > 0) {
-        hip_check(c, hipMemcpyAsync(d_dbase, dbase.data(), sizeof(int64_t) * (GD + 1),
+        hip_check(c, hipMemcpyAsync(d_dbase, B.dbase.data(), sizeof(int64_t) * (GD + 1),
                                     hipMemcpyHostToDevice, st),
                   "upload dual bases");
-        hip_check(c, hipMemcpyAsync(d_dual_ids, dual_ids.data(), sizeof(int32_t) * GD,
+        hip_check(c, hipMemcpyAsync(d_dual_ids, B.dual_ids.data(), sizeof(int32_t) * GD,
                                     hipMemcpyHostToDevice, st),
                   "upload dual ids");
     }
     // 3. XD and its transpose; 4. combined item CSR
     Arena sz;
-    auto plan = [&](Arena &A, Layout &X, int32_t *&len, int32_t *&ptrC,
-                    int32_t *&memC, int32_t *&s_item, int32_t *&iend) {
-        X.rowid = A.take<int32_t>(ZD);
-        X.colT = A.take<int32_t>(ZD);
-        X.ptrT = A.take<int32_t>(VD + 1);
-        X.rsK0 = A.take<int32_t>(ZD);
-        X.rsK1 = A.take<int32_t>(ZD);
-        X.rsV0 = A.take<int32_t>(ZD);
-        X.rsV1 = A.take<int32_t>(ZD);
-        X.rsHist = A.take<int32_t>(16 * transpose_tiles(ZD) + 1);
-        X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>({VD, NI, ZD}) + 1));
-        len = A.take<int32_t>(NI);
-        ptrC = A.take<int32_t>(NI + 1);
-        memC = A.take<int32_t>(ZT);
-        s_item = A.take<int32_t>(NI);
-        iend = A.take<int32_t>(NI);
-        X.xcol = A.take<int32_t>(ZD);
-    };
-    Layout X{};
-    int32_t *len, *ptrC, *memC, *s_item, *iend;
-    plan(sz, X, len, ptrC, memC, s_item, iend);
+    (void)plan_combine(sz, B);
     void *big = dev_alloc(c, sz.off + 4096);
     if (!big) {
         set_err(c, "batch arrays allocation failed");
@@ -1239,24 +1311,8 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     try {
         Arena A;
         A.base = reinterpret_cast<char *>(big);
-        plan(A, X, len, ptrC, memC, s_item, iend);
-        int32_t *xcol = X.xcol;
-        hip_check(c, launch_fill_i32(st, xcol, ZD, 0), "zero dual columns");
-        hip_check(c, launch_fill_i32(st, X.rowid, ZD, 0), "zero dual rows");
-        if (GD > 0 && E > 0) {
-            hip_check(c, launch_batch_concat(st, d_gr, d_dual_ids, d_dbase, GD, E, xcol, X.rowid,
-                                             d_err),
-                      "dual rows");
-            if (ZD > 0) transpose(c, X, xcol, (int32_t)VD, ZD);
-            else hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
-        } else if (VD > 0) {
-            hip_check(c, launch_fill_i32(st, X.ptrT, VD + 1, 0), "empty transpose");
-        }
-        hip_check(c, launch_batch_len(st, d_gr, P.ibase_dev, G, NI, X.ptrT, len, s_item, iend, d_err),
-                  "item lengths");
-        hip_check(c, launch_scan_i32(st, len, NI, ptrC, X.part32), "item scan");
-        hip_check(c, launch_batch_rows(st, d_gr, P.ibase_dev, G, ZT, X.ptrT, X.colT, ptrC, d_zb, memC),
-                  "item rows");
+        const Combine K = plan_combine(A, B);
+        enqueue_combine(c, st, G, B, BatchDev{d_gr, P.ibase_dev, d_dbase, d_dual_ids, d_zb, d_err}, K);
         hip_check(c, hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
                   "read flags");
         sync(c, "batch items");
@@ -1268,13 +1324,13 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
         }
         // 5. one pass of the pipeline over the combined items, each with its own s
         sline_csr CH{};
-        CH.row_ptr = ptrC;
-        CH.col_idx = memC;
+        CH.row_ptr = K.ptrC;
+        CH.col_idx = K.memC;
         CH.n_edges = (int32_t)NI;
         CH.n_vertices = (int32_t)std::max<int64_t>(MT, 1);
         ItemS IS;
-        IS.s_item = s_item;
-        IS.item_end = iend;
+        IS.s_item = K.s_item;
+        IS.item_end = K.iend;
         IS.s_min = s_min;
         IS.s_max = s_max;
         // library-allocated outputs of several graphs: the fill writes them
@@ -1329,6 +1385,557 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
     const sline_status r = batch_split(c, G, outs);
     if (r == SLINE_OK) drop_batch_pending(c);
     return r;
+}
+
+// ------------------------------------------------------------ batch plans
+//
+// A batch whose every buffer is sized once, so that the whole pipeline --
+// shape checks, combine stage, transpose, s filter, costs, tasks, one
+// counting pass with staging, pair scan, staged copy, recount of tasks that
+// found no room, per-graph offsets -- is captured as one HIP graph.  Sizes
+// that depend on the data (tasks, pairs) are the ones counted when the plan
+// was made; guard kernels compare each run's counts with them and, when a
+// count is larger, set a bit that makes every later kernel of the run return
+// at once, so that no kernel writes past its buffer.
+
+}  // namespace
+
+struct sline_batch_plan {
+    sline_ctx *c = nullptr;
+    int32_t G = 0;
+    uint32_t flags = 0;
+    bool weights = true;
+    std::vector<BatchGraph> gr;        // descriptors as last uploaded
+    std::vector<int32_t> s_plan;       // each graph's planned s
+    BatchBases B;
+    int32_t s_min = 1;
+    std::vector<std::pair<void *, size_t>> mem;  // device allocations
+    // device views
+    BatchGraph *d_gr = nullptr;
+    int64_t *d_nnz = nullptr, *ibase = nullptr, *dbase = nullptr, *off = nullptr;
+    int32_t *d_err = nullptr, *dual_ids = nullptr, *zb = nullptr;
+    Combine K;
+    Layout L{};
+    TaskLayout TL{};
+    CountArgs C{};
+    int64_t t_cap = 0, pair_cap = 0, pool_cap = 0;
+    int32_t *pool = nullptr, *out_a = nullptr, *out_b = nullptr, *out_w = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t *host = nullptr;  // pinned read-back: off (G + 1 words), then 16 words
+};
+
+namespace {
+
+void plan_free(sline_batch_plan *p) {
+    if (!p) return;
+    sline_ctx *c = p->c;
+    if (c) (void)hipStreamSynchronize(c->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    for (auto &m : p->mem) dev_free(c, m.first, m.second);
+    if (c) (void)hipStreamSynchronize(c->stream);
+    if (p->host) (void)hipHostFree(p->host);
+    delete p;
+}
+
+void *plan_alloc(sline_batch_plan *p, size_t bytes, const char *what) {
+    void *q = dev_alloc(p->c, bytes);
+    if (!q) {
+        set_err(p->c, "batch plan: allocation of %s failed", what);
+        throw Fail{SLINE_ENOMEM};
+    }
+    p->mem.emplace_back(q, bytes);
+    return q;
+}
+
+BatchDev plan_dev(sline_batch_plan *p) {
+    return BatchDev{p->d_gr, p->ibase, p->dbase, p->dual_ids, p->zb, p->d_err};
+}
+
+// Shape checks, combine stage, transposes, filter, costs, lookup-only members
+// and the task scan; with t_cap >= 0, the guard of the task count.
+void plan_enqueue_prep(sline_batch_plan *p, hipStream_t st, int64_t t_cap) {
+    sline_ctx *c = p->c;
+    const BatchBases &B = p->B;
+    hip_check(c, launch_fill_i32(st, p->d_err, 4, 0), "zero flags");
+    hip_check(c, launch_plan_check_shape(st, p->d_gr, p->G, p->d_err), "shape check");
+    if (B.ZT == 0) {
+        hip_check(c, launch_fill_i64(st, p->off, p->G + 1, 0), "zero offsets");
+        return;
+    }
+    enqueue_combine(c, st, p->G, B, plan_dev(p), p->K);
+    const Layout &L = p->L;
+    const int32_t NI = (int32_t)B.NI, MT = (int32_t)B.MT;
+    const int32_t *ptrI = p->K.ptrC, *memI = p->K.memC;
+    hip_check(c, launch_fill_i32(st, L.err, 4, 0), "zero flags");
+    hip_check(c, launch_fill_i32(st, L.tcounts, 4, 0), "zero task counts");
+    hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
+    hip_check(c, launch_fill_i64(st, L.passes, 4, 0), "zero passes");
+    hip_check(c, launch_rows(st, ptrI, memI, NI, MT, B.ZT, 0, L.rowid, L.err), "row ids");
+    int32_t *const rk[2] = {L.rsK0, L.rsK1};
+    int32_t *const rv[2] = {L.rsV0, L.rsV1};
+    hip_check(c, launch_transpose(st, memI, B.ZT, MT, L.rowid, rk, rv, L.rsHist, L.part32, L.ptrT,
+                                  L.colT, L.kT, L.posT),
+              "transpose");
+    // every item carries its graph's s; the filter, the costs and the
+    // lookup-only members read them per item, so a run's s need not be the
+    // planned one
+    hip_check(c, launch_filter(st, L.ptrT, L.colT, MT, B.ZT, ptrI, p->s_min, p->K.s_item, L.pos,
+                               L.part32, L.ptrS, L.itmS, L.kT, L.start),
+              "filter");
+    hip_check(c, launch_cost(st, ptrI, memI, NI, p->s_min, p->K.s_item, L.ptrS, L.itmS, L.cost,
+                             L.start, L.totals, 0, 1),
+              "cost");
+    hip_check(c, launch_mark_lookup(st, ptrI, memI, NI, p->s_min, p->K.s_item, INT32_MAX, L.ptrS,
+                                    L.start, L.cost),
+              "lookup members");
+    const Tuning &tu = p->C.tune;
+    hip_check(c, launch_task_count(st, L.cost, NI, tu, ptrI, p->K.iend, 0, L.ntask), "task count");
+    hip_check(c, launch_scan_i32_to_i64(st, L.ntask, NI, L.tbase, L.part64), "task scan");
+    if (t_cap >= 0)
+        hip_check(c, launch_plan_guard(st, L.tbase + NI, t_cap, kErrPlanTasks, p->d_err), "task guard");
+}
+
+// Task lists, the counting pass (staging into the pool) and the pair scan;
+// with pair_cap >= 0, the guard of the pair count.
+void plan_enqueue_count(sline_batch_plan *p, hipStream_t st, int64_t pair_cap) {
+    if (p->B.ZT == 0) return;
+    sline_ctx *c = p->c;
+    const Layout &L = p->L;
+    const TaskLayout &TL = p->TL;
+    const CountArgs &C = p->C;
+    const int32_t NI = (int32_t)p->B.NI;
+    hip_check(c, launch_task_fill(st, L.cost, NI, C.tune, C.ptrI, p->K.iend, 0, L.tbase, TL.item,
+                                  TL.part, TL.small, TL.small_item, TL.big, L.tcounts, p->d_err),
+              "task fill");
+    hip_check(c, launch_fill_i32(st, TL.need, p->t_cap, 0), "zero need flags");
+    hip_check(c, launch_fill_i32(st, reinterpret_cast<int32_t *>(TL.log),
+                                 (int64_t)TL.log_cap * (int64_t)(sizeof(StageRec) / 4), 0),
+              "zero log");
+    hip_check(c, launch_fill_i32(st, TL.ctrs, 4, 0), "zero counters");
+    hip_check(c, launch_fill_i64(st, reinterpret_cast<int64_t *>(TL.pool_head), 1, 0),
+              "zero pool head");
+    // tasks beyond this run's count must add no pairs to the scan
+    hip_check(c, launch_fill_i32(st, TL.cnt, p->t_cap, 0), "zero pair counts");
+    hip_check(c, launch_count(st, C), "count pass");
+    hip_check(c, launch_scan_i32_to_i64(st, TL.cnt, p->t_cap, TL.off, TL.part64), "pair scan");
+    if (pair_cap >= 0)
+        hip_check(c, launch_plan_guard(st, TL.off + p->t_cap, pair_cap, kErrPlanPairs, p->d_err),
+                  "pair guard");
+}
+
+// Staged ranges to the result arrays (each graph's ids less its item base),
+// recount of the tasks that found no room, and the per-graph offsets.
+void plan_enqueue_fill(sline_batch_plan *p, hipStream_t st) {
+    if (p->B.ZT == 0) return;
+    sline_ctx *c = p->c;
+    CountArgs F = p->C;
+    F.task_off = p->TL.off;
+    F.passes = nullptr;
+    F.out_a = p->out_a;
+    F.out_b = p->out_b;
+    F.out_w = p->weights ? p->out_w : nullptr;
+    F.n_graphs = p->G;
+    F.g_ibase = p->ibase;
+    F.g_off = nullptr;
+    F.g_out = nullptr;
+    if (F.mode == kModeStage) {
+        hip_check(c, launch_stage_copy(st, F, -1), "stage copy");
+        F.mode = kModeFill;  // only the flagged tasks, and nothing when none is
+    } else {
+        F.mode = kModeFill;
+        F.need = nullptr;
+    }
+    hip_check(c, launch_count(st, F), "fill pass");
+    hip_check(c, launch_batch_graph_off(st, p->TL.item, (int32_t)p->t_cap, p->TL.off, p->ibase,
+                                        p->G, p->off, p->L.tbase + p->B.NI),
+              "graph pair offsets");
+}
+
+// Counting arguments of the plan's pass (mode, pool and chunks set by the caller).
+CountArgs plan_count_args(sline_batch_plan *p) {
+    const Layout &L = p->L;
+    const TaskLayout &TL = p->TL;
+    CountArgs C = p->C;  // keeps the tuning
+    C.ptrI = p->K.ptrC;
+    C.memI = p->K.memC;
+    C.ptrS = L.ptrS;
+    C.itmS = L.itmS;
+    C.N = (int32_t)p->B.NI;
+    C.s = p->s_min;
+    C.s_item = p->K.s_item;
+    C.item_end = p->K.iend;
+    C.full = 0;
+    C.cost = L.cost;
+    C.start = L.start;
+    C.task_item = TL.item;
+    C.task_part = TL.part;
+    C.n_tasks = (int32_t)p->t_cap;
+    C.small_tasks = TL.small;
+    C.small_items = TL.small_item;
+    C.big_tasks = TL.big;
+    C.task_counts = L.tcounts;
+    C.queue = L.queue;
+    C.task_cnt = TL.cnt;
+    C.task_off = nullptr;
+    C.pool_b = p->pool;
+    C.pool_w = (p->pool && p->weights) ? p->pool + p->pool_cap : nullptr;
+    C.pool_cap = p->pool_cap;
+    C.pool_head = TL.pool_head;
+    C.log = TL.log;
+    C.log_cap = TL.log_cap;
+    C.log_head = TL.ctrs;
+    C.need = TL.need;
+    C.need_count = TL.ctrs + 1;
+    C.passes = L.passes;
+    C.err = L.err;
+    C.n_cu = p->c->n_cu;
+    C.abort = p->d_err;
+    C.mode = p->pool_cap > 0 ? kModeStage : kModeCount;
+    const int64_t groups =
+        (int64_t)C.n_cu * (C.tune.small_grid_per_cu + C.tune.task_grid_per_cu);
+    C.pool_chunk = std::max<int64_t>(256, std::min<int64_t>(1 << 16, p->pool_cap / (8 * groups)));
+    C.log_chunk =
+        (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)TL.log_cap / (8 * groups)));
+    return C;
+}
+
+// Staging pool of `pairs` pairs (halving on failure); 0 pairs: no pool.
+void plan_pool(sline_batch_plan *p, int64_t pairs) {
+    const int64_t pair_bytes = p->weights ? 8 : 4;
+    int64_t cap = std::min<int64_t>(pairs, p->C.tune.stage_max_bytes / pair_bytes);
+    p->pool = nullptr;
+    p->pool_cap = 0;
+    while (cap >= 256) {
+        void *q = dev_alloc(p->c, (size_t)(cap * pair_bytes));
+        if (q) {
+            p->mem.emplace_back(q, (size_t)(cap * pair_bytes));
+            p->pool = reinterpret_cast<int32_t *>(q);
+            p->pool_cap = cap;
+            return;
+        }
+        cap /= 2;
+    }
+}
+
+void plan_drop_last(sline_batch_plan *p, void *q) {
+    for (size_t i = 0; i < p->mem.size(); ++i) {
+        if (p->mem[i].first == q) {
+            (void)hipStreamSynchronize(p->c->stream);
+            dev_free(p->c, q, p->mem[i].second);
+            p->mem.erase(p->mem.begin() + (long)i);
+            return;
+        }
+    }
+}
+
+sline_status plan_csr_error(sline_ctx *c, int32_t e) {
+    if (e & kErrPlanShape)
+        set_err(c, "batch plan: a graph's row_ptr[0] or row_ptr[m] differs from the planned one");
+    else
+        set_err(c, "a graph breaks the CSR rules (row_ptr order, member range or order)");
+    return SLINE_EINVAL;
+}
+
+sline_status plan_create_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int32_t *s,
+                              const int32_t *dual, uint32_t flags, sline_batch_plan **out) {
+    if (!out) {
+        set_err(c, "plan is NULL");
+        return SLINE_EINVAL;
+    }
+    *out = nullptr;
+    if (flags & ~(uint32_t)SLINE_NO_WEIGHTS) {
+        set_err(c, "batch plans take no flag but SLINE_NO_WEIGHTS");
+        return SLINE_EINVAL;
+    }
+    if (G < 0 || (G > 0 && (!Hs || !s || !dual))) {
+        set_err(c, "invalid batch arguments");
+        return SLINE_EINVAL;
+    }
+    for (int32_t g = 0; g < G; ++g) {
+        const sline_csr &H = Hs[g];
+        if (s[g] < 1 || (dual[g] != 0 && dual[g] != 1) || H.n_edges < 0 || H.n_vertices < 0 ||
+            (H.n_edges > 0 && !H.row_ptr)) {
+            set_err(c, "invalid arguments for graph %s", std::to_string(g).c_str());
+            return SLINE_EINVAL;
+        }
+    }
+    std::unique_ptr<sline_batch_plan, void (*)(sline_batch_plan *)> P(new sline_batch_plan,
+                                                                        plan_free);
+    sline_batch_plan *p = P.get();
+    p->c = c;
+    p->G = G;
+    p->flags = flags;
+    p->weights = (flags & SLINE_NO_WEIGHTS) == 0;
+    p->C.tune = c->tune;
+    if (hipHostMalloc((void **)&p->host, sizeof(int64_t) * ((size_t)G + 17), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        p->host = nullptr;
+        set_err(c, "batch plan: pinned host allocation failed");
+        return SLINE_ENOMEM;
+    }
+    hipStream_t st = c->stream;
+    // 1. descriptors and the graphs' nnz
+    p->gr.resize(G);
+    p->s_plan.assign(s, s + G);
+    int32_t s_min = INT32_MAX;
+    for (int32_t g = 0; g < G; ++g) {
+        BatchGraph &d = p->gr[g];
+        d = BatchGraph{};
+        d.rp = Hs[g].row_ptr;
+        d.col = Hs[g].col_idx;
+        d.m = Hs[g].n_edges;
+        d.n = Hs[g].n_vertices;
+        d.dual = dual[g];
+        d.s = s[g];
+        s_min = std::min(s_min, s[g]);
+    }
+    p->s_min = G > 0 ? s_min : 1;
+    {
+        Arena W;
+        const size_t small = sizeof(BatchGraph) * (size_t)std::max(G, 1) + 8 * (size_t)(5 * G + 16) + 4096;
+        W.base = reinterpret_cast<char *>(plan_alloc(p, small, "descriptors"));
+        p->d_gr = W.take<BatchGraph>(G);
+        p->d_nnz = W.take<int64_t>(G);
+        p->d_err = W.take<int32_t>(4);
+        p->ibase = W.take<int64_t>(G + 1);
+        p->off = W.take<int64_t>(G + 1);
+        p->dbase = W.take<int64_t>(G + 1);
+        p->dual_ids = W.take<int32_t>(G);
+        p->zb = W.take<int32_t>(G + 1);
+    }
+    std::vector<int64_t> nnz(G, 0);
+    if (G > 0) {
+        hip_check(c, launch_fill_i32(st, p->d_err, 4, 0), "zero flags");
+        hip_check(c, hipMemcpyAsync(p->d_gr, p->gr.data(), sizeof(BatchGraph) * G,
+                                    hipMemcpyHostToDevice, st),
+                  "upload graphs");
+        hip_check(c, launch_batch_nnz(st, p->d_gr, G, p->d_nnz, p->d_err), "batch nnz");
+        hip_check(c, hipMemcpyAsync(nnz.data(), p->d_nnz, sizeof(int64_t) * G,
+                                    hipMemcpyDeviceToHost, st),
+                  "read nnz");
+        hip_check(c, hipMemcpyAsync(p->host, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "batch nnz");
+        if (reinterpret_cast<const int32_t *>(p->host)[0]) {
+            set_err(c, "row_ptr must start at 0 in every graph");
+            return SLINE_EINVAL;
+        }
+    }
+    // 2. bases, combine and build arrays
+    const sline_status rb = batch_bases(c, p->gr, nnz, p->B);
+    if (rb != SLINE_OK) return rb;
+    const BatchBases &B = p->B;
+    if (G > 0) {
+        hip_check(c, hipMemcpyAsync(p->d_gr, p->gr.data(), sizeof(BatchGraph) * G,
+                                    hipMemcpyHostToDevice, st),
+                  "upload graphs");
+        hip_check(c, hipMemcpyAsync(p->ibase, B.ibase.data(), sizeof(int64_t) * (G + 1),
+                                    hipMemcpyHostToDevice, st),
+                  "upload item bases");
+        if (B.GD() > 0) {
+            hip_check(c, hipMemcpyAsync(p->dbase, B.dbase.data(), sizeof(int64_t) * (B.GD() + 1),
+                                        hipMemcpyHostToDevice, st),
+                      "upload dual bases");
+            hip_check(c, hipMemcpyAsync(p->dual_ids, B.dual_ids.data(), sizeof(int32_t) * B.GD(),
+                                        hipMemcpyHostToDevice, st),
+                      "upload dual ids");
+        }
+    }
+    if (B.ZT > 0) {
+        Arena sz;
+        (void)plan_combine(sz, B);
+        (void)plan_layout(sz, B.NI, B.MT, B.ZT, B.NI, B.MT, true);
+        Arena A;
+        A.base = reinterpret_cast<char *>(plan_alloc(p, sz.off + 4096, "the batch arrays"));
+        p->K = plan_combine(A, B);
+        p->L = plan_layout(A, B.NI, B.MT, B.ZT, B.NI, B.MT, true);
+        p->C.ptrI = p->K.ptrC;
+    }
+    // 3. one run of the preparation, without guards: the task count
+    if (G > 0) {
+        plan_enqueue_prep(p, st, -1);
+        int64_t *h = p->host;
+        if (B.ZT > 0) {
+            hip_check(c, hipMemcpyAsync(h + 0, p->L.tbase + B.NI, sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, st),
+                      "read tasks");
+            hip_check(c, hipMemcpyAsync(h + 1, p->L.totals, 3 * sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, st),
+                      "read totals");
+        }
+        hip_check(c, hipMemcpyAsync(h + 4, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "batch plan tasks");
+        const int32_t e = reinterpret_cast<const int32_t *>(h + 4)[0];
+        if (e) return plan_csr_error(c, e);
+    }
+    if (B.ZT > 0) {
+        const int64_t T = p->host[0], wedges = p->host[3];
+        if (T >= INT32_MAX) {
+            set_err(c, "too many counting tasks (%s)", std::to_string(T).c_str());
+            return SLINE_ENOMEM;
+        }
+        p->t_cap = std::max<int64_t>(T, 1);
+        {
+            Arena sz;
+            (void)plan_tasks(sz, p->t_cap);
+            Arena A;
+            A.base = reinterpret_cast<char *>(plan_alloc(p, sz.off + 4096, "the task arrays"));
+            p->TL = plan_tasks(A, p->t_cap);
+        }
+        // 4. one counting pass with a pool of W_s / s_min pairs (every pair
+        // of L_s takes at least s wedges): the pair count
+        plan_pool(p, wedges / p->s_min);
+        void *first_pool = p->pool;
+        p->C = plan_count_args(p);
+        plan_enqueue_count(p, st, -1);
+        int64_t *h = p->host;
+        hip_check(c, hipMemcpyAsync(h + 0, p->TL.off + p->t_cap, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, st),
+                  "read pairs");
+        hip_check(c, hipMemcpyAsync(h + 1, p->L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        sync(c, "batch plan pairs");
+        if (reinterpret_cast<const int32_t *>(h + 1)[0] & kErrInternal) {
+            set_err(c, "internal error: counting table overflow");
+            return SLINE_EDEVICE;
+        }
+        const int64_t total = h[0];
+        p->pair_cap = std::max<int64_t>(total, 1);
+        // the pool kept for the runs, instead of the W_s / s_min bound: a
+        // range that does not fit its workgroup's chunk leaves less than its
+        // own size unused, so the pairs take at most twice their number plus
+        // the chunks left partly used at the end (one per workgroup, at most
+        // an eighth of the pool in all); tasks that still find no room are
+        // counted again by the fill pass
+        const int64_t groups =
+            (int64_t)c->n_cu * (p->C.tune.small_grid_per_cu + p->C.tune.task_grid_per_cu);
+        const int64_t keep = std::min<int64_t>(p->pool_cap, total * 7 / 3 + 512 * groups);
+        if (first_pool && keep < p->pool_cap) {
+            plan_drop_last(p, first_pool);
+            plan_pool(p, keep);
+        }
+        p->C = plan_count_args(p);
+        const size_t bytes = sizeof(int32_t) * (size_t)p->pair_cap;
+        p->out_a = reinterpret_cast<int32_t *>(plan_alloc(p, bytes, "the result arrays"));
+        p->out_b = reinterpret_cast<int32_t *>(plan_alloc(p, bytes, "the result arrays"));
+        if (p->weights)
+            p->out_w = reinterpret_cast<int32_t *>(plan_alloc(p, bytes, "the result arrays"));
+    }
+    // 5. capture every stage, with the guards, on a stream of the plan's own
+    // (the context's stream may be the null stream, which cannot capture)
+    sync(c, "batch plan buffers");
+    if (G == 0) {
+        *out = P.release();
+        return SLINE_OK;
+    }
+    hip_check(c, hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking), "capture stream");
+    hip_check(c, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+        plan_enqueue_prep(p, p->cap, p->t_cap);
+        plan_enqueue_count(p, p->cap, p->pair_cap);
+        plan_enqueue_fill(p, p->cap);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(p->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        throw;
+    }
+    hip_check(c, hipStreamEndCapture(p->cap, &p->graph), "end capture");
+    hip_check(c, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "graph instantiate");
+    *out = P.release();
+    return SLINE_OK;
+}
+
+sline_status plan_run_impl(sline_batch_plan *p, const int32_t *s, sline_edges *outs) {
+    sline_ctx *c = p->c;
+    const int32_t G = p->G;
+    if (G > 0 && !outs) {
+        set_err(c, "outs is NULL");
+        return SLINE_EINVAL;
+    }
+    if (G == 0) return SLINE_OK;
+    hipStream_t st = c->stream;
+    bool changed = false;
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t want = s ? s[g] : p->s_plan[g];
+        if (want < p->s_plan[g]) {
+            set_err(c, "batch plan: graph %s asks for an s below its planned s",
+                    std::to_string(g).c_str());
+            return SLINE_EINVAL;
+        }
+        changed = changed || want != p->gr[g].s;
+        p->gr[g].s = want;
+    }
+    if (changed)
+        hip_check(c, hipMemcpyAsync(p->d_gr, p->gr.data(), sizeof(BatchGraph) * G,
+                                    hipMemcpyHostToDevice, st),
+                  "upload graphs");
+    hip_check(c, hipGraphLaunch(p->exec, st), "graph launch");
+    int64_t *h = p->host;
+    int64_t *w = h + G + 1;
+    hip_check(c, hipMemcpyAsync(h, p->off, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, st),
+              "read offsets");
+    hip_check(c, hipMemcpyAsync(w, p->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+              "read flags");
+    if (p->B.ZT > 0) {
+        hip_check(c, hipMemcpyAsync(w + 1, p->L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "read flags");
+        hip_check(c, hipMemcpyAsync(w + 2, p->L.totals, 3 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    st),
+                  "read totals");
+        hip_check(c, hipMemcpyAsync(w + 5, p->L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st),
+                  "read passes");
+    } else {
+        w[1] = 0;
+    }
+    sync(c, "batch plan run");
+    const int32_t e = reinterpret_cast<const int32_t *>(w)[0];
+    if (e & (kErrPlanTasks | kErrPlanPairs)) {
+        set_err(c, "batch plan: the run needs more %s than the plan holds; make a new plan",
+                (e & kErrPlanTasks) ? "counting tasks" : "pairs");
+        return SLINE_ECAPACITY;
+    }
+    if (e) return plan_csr_error(c, e);
+    if (reinterpret_cast<const int32_t *>(w + 1)[0] & kErrInternal) {
+        set_err(c, "internal error: counting table overflow");
+        return SLINE_EDEVICE;
+    }
+    if (h[0] != 0 || h[G] > p->pair_cap) {
+        set_err(c, "internal error: graph pair offsets out of range");
+        return SLINE_EDEVICE;
+    }
+    for (int32_t g = 0; g < G; ++g) {
+        const int64_t n = h[g + 1] - h[g];
+        if (n < 0) {
+            set_err(c, "internal error: graph pair offsets out of order");
+            return SLINE_EDEVICE;
+        }
+        sline_edges &o = outs[g];
+        o.n_pairs = n;
+        o.capacity = 0;
+        o.a = p->out_a ? p->out_a + h[g] : nullptr;
+        o.b = p->out_b ? p->out_b + h[g] : nullptr;
+        o.w = p->out_w ? p->out_w + h[g] : nullptr;
+    }
+    sline_stats S{};
+    S.n_items = p->B.NI;
+    S.nnz = p->B.ZT;
+    if (p->B.ZT > 0) {
+        S.n_kept = w[2];
+        S.nnz_kept = w[3];
+        S.wedges = w[4];
+        S.passes = w[5];
+    }
+    S.n_pairs = h[G];
+    c->stats = S;
+    return SLINE_OK;
 }
 
 // ------------------------------------------------------ SpGEMM companion
@@ -2249,6 +2856,63 @@ sline_status sline_build_batch(sline_ctx *c, int32_t n_graphs, const sline_csr *
         set_err(c, "host allocation failed");
         return SLINE_ENOMEM;
     }
+}
+
+sline_status sline_batch_plan_create(sline_ctx *c, int32_t n_graphs, const sline_csr *Hs,
+                                     const int32_t *s, const int32_t *dual, uint32_t flags,
+                                     sline_batch_plan **plan) {
+    if (plan) *plan = nullptr;
+    if (!c) return SLINE_EINVAL;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return plan_create_impl(c, n_graphs, Hs, s, dual, flags, plan);
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_batch_plan_run(sline_batch_plan *p, const int32_t *s, sline_edges *outs) {
+    if (!p || !p->c) return SLINE_EINVAL;
+    sline_ctx *c = p->c;
+    c->last_error.clear();
+    if (hipSetDevice(c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(c, "hipSetDevice failed");
+        return SLINE_EDEVICE;
+    }
+    try {
+        return plan_run_impl(p, s, outs);
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        set_err(c, "host allocation failed");
+        return SLINE_ENOMEM;
+    }
+}
+
+sline_status sline_batch_plan_info(const sline_batch_plan *p, int64_t *device_bytes,
+                                   int64_t *task_capacity, int64_t *pair_capacity) {
+    if (!p) return SLINE_EINVAL;
+    int64_t bytes = 0;
+    for (const auto &m : p->mem) bytes += (int64_t)m.second;
+    if (device_bytes) *device_bytes = bytes;
+    if (task_capacity) *task_capacity = p->t_cap;
+    if (pair_capacity) *pair_capacity = p->pair_cap;
+    return SLINE_OK;
+}
+
+void sline_batch_plan_destroy(sline_batch_plan *p) {
+    if (!p) return;
+    if (p->c) (void)hipSetDevice(p->c->device);
+    plan_free(p);
 }
 
 sline_status sline_build_spgemm(sline_ctx *c, sline_csr H, int32_t s, int32_t dual, uint32_t flags,

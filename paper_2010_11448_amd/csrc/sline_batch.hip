@@ -60,6 +60,7 @@ __global__ void k_batch_nnz(const BatchGraph *gr, int32_t G, int64_t *nnz, int32
 __global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, const int32_t *dual_ids,
                                                       const int64_t *dbase, int32_t GD, int64_t E,
                                                       int32_t *xcol, int32_t *xrow, int32_t *err) {
+    if (*err & kErrPlanShape) return;  // a replayed plan keeps its last lists
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(256) void k_batch_concat(const BatchGraph *gr, cons
 __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t G, int64_t NI,
                             const int32_t *ptrT, int32_t *len, int32_t *s_item, int32_t *item_end,
                             int32_t *err) {
+    if (*err & kErrPlanShape) return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < NI;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t g = find_graph(ibase, G, i);
@@ -137,7 +139,9 @@ __global__ void k_batch_zbase(const int64_t *ibase, int32_t G, const int32_t *pt
 // combined member ids; a dual graph's are its block of XD^T (rows of its
 // vertices), whose entries are combined row ids of XD turned into member ids.
 __global__ void k_batch_rows(const BatchGraph *gr, const int32_t *zb, int32_t G, int64_t ZT,
-                             const int32_t *ptrT, const int32_t *colT, int32_t *memC) {
+                             const int32_t *ptrT, const int32_t *colT, int32_t *memC,
+                             const int32_t *err) {
+    if (*err & kErrPlanShape) return;
     for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < ZT;
          z += (int64_t)gridDim.x * blockDim.x) {
         int32_t lo = 0, hi = G;  // zb[lo] <= z < zb[hi]
@@ -196,9 +200,11 @@ __global__ void k_batch_split(const int64_t *ibase, const int64_t *off, int32_t 
 
 // One thread per graph boundary g = 0..G: the first pair of graph g.
 __global__ void k_batch_graph_off(const int32_t *task_item, int32_t T, const int64_t *task_off,
-                                  const int64_t *g_ibase, int32_t G, int64_t *g_off) {
+                                  const int64_t *g_ibase, int32_t G, int64_t *g_off,
+                                  const int64_t *T_dev) {
     const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g > G) return;
+    if (T_dev) T = (int32_t)min(*T_dev, (int64_t)T);
     const int64_t first = g_ibase[g];
     int32_t lo = 0, hi = T;  // first task with task_item >= first
     while (lo < hi) {
@@ -209,14 +215,39 @@ __global__ void k_batch_graph_off(const int32_t *task_item, int32_t T, const int
     g_off[g] = task_off[lo];
 }
 
+// Replayed plans: the caller's row_ptr must still start at 0 and end at the
+// nnz the plan was sized for (every later kernel bounds its reads by it).
+__global__ void k_plan_check_shape(const BatchGraph *gr, int32_t G, int32_t *err) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const BatchGraph d = gr[g];
+    if (d.m > 0 && (d.rp[0] != 0 || (int64_t)d.rp[d.m] != d.nnz)) atomicOr(err, kErrPlanShape);
+}
+
+__global__ void k_plan_guard(const int64_t *value, int64_t cap, int32_t bit, int32_t *err) {
+    if (threadIdx.x == 0 && *value > cap) atomicOr(err, bit);
+}
+
 }  // namespace
 
 hipError_t launch_batch_graph_off(hipStream_t st, const int32_t *task_item, int32_t n_tasks,
                                   const int64_t *task_off, const int64_t *g_ibase, int32_t G,
-                                  int64_t *g_off) {
+                                  int64_t *g_off, const int64_t *n_tasks_dev) {
     if (G <= 0) return hipSuccess;
     k_batch_graph_off<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(task_item, n_tasks, task_off,
-                                                                     g_ibase, G, g_off);
+                                                                     g_ibase, G, g_off, n_tasks_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_check_shape(hipStream_t st, const BatchGraph *gr, int32_t G, int32_t *err) {
+    if (G <= 0) return hipSuccess;
+    k_plan_check_shape<<<grid_for(G, 256), 256, 0, st>>>(gr, G, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_guard(hipStream_t st, const int64_t *value, int64_t cap, int32_t bit,
+                             int32_t *err) {
+    k_plan_guard<<<1, kWave, 0, st>>>(value, cap, bit, err);
     return hipGetLastError();
 }
 
@@ -247,12 +278,12 @@ hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t 
 
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                              int64_t ZT, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *zb, int32_t *memC) {
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC, const int32_t *err) {
     if (G <= 0) return hipSuccess;
     k_batch_zbase<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(ibase, G, ptrC, zb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ZT <= 0) return e;
-    k_batch_rows<<<grid_for(ZT, 256, 65536), 256, 0, st>>>(gr, zb, G, ZT, ptrT, colT, memC);
+    k_batch_rows<<<grid_for(ZT, 256, 65536), 256, 0, st>>>(gr, zb, G, ZT, ptrT, colT, memC, err);
     return hipGetLastError();
 }
 

@@ -523,11 +523,13 @@ __device__ __forceinline__ OutDst out_dst(const CountArgs &A, int32_t item, int6
             if (A.g_ibase[mid] <= item) lo = mid;
             else hi = mid;
         }
-        d.a = A.g_out[lo];
-        d.b = A.g_out[G + lo];
-        d.w = A.g_out[2 * G + lo];
-        d.base = pos - A.g_off[lo];
         d.shift = (int32_t)A.g_ibase[lo];
+        if (A.g_out) {
+            d.a = A.g_out[lo];
+            d.b = A.g_out[G + lo];
+            d.w = A.g_out[2 * G + lo];
+            d.base = pos - A.g_off[lo];
+        }
     }
     return d;
 }
@@ -983,6 +985,14 @@ constexpr int kTaskPad = 64;
 constexpr int kTaskRunCap = 256;
 constexpr int kStack = 64;
 
+// A counting launch with nothing to do: the plan's bounds were exceeded (or
+// its input is malformed), or a fill pass that only recounts tasks flagged in
+// `need` while none is flagged.
+__device__ __forceinline__ bool count_idle(const CountArgs &A) {
+    if (A.abort && *A.abort != 0) return true;
+    return A.mode == kModeFill && A.need && A.need_count && *A.need_count == 0;
+}
+
 // --------------------------------------------------------------- small
 
 __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
@@ -995,6 +1005,7 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
     __shared__ uint64_t pool_cur[2];
     __shared__ int32_t log_cur[2];
     const Smem S{tab, runs, taken, misc, stack, tab + LIM, pool_cur, log_cur};
+    if (count_idle(A)) return;  // uniform: every thread reads the same words
     if (threadIdx.x == 0) {
         pool_cur[0] = pool_cur[1] = 0;
         log_cur[0] = log_cur[1] = 0;
@@ -1040,6 +1051,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
     __shared__ uint64_t pool_cur[2];
     __shared__ int32_t log_cur[2];
     const Smem S{tab, runs, taken, misc, stack, tab + LIM, pool_cur, log_cur};
+    if (count_idle(A)) return;  // uniform: every thread reads the same words
     if (threadIdx.x == 0) {
         pool_cur[0] = pool_cur[1] = 0;
         log_cur[0] = log_cur[1] = 0;
@@ -1155,7 +1167,8 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
                                                    int32_t *task_item, int32_t *task_part,
                                                    int32_t *small_tasks, int32_t *small_items,
                                                    int32_t *groups, int32_t *counts,
-                                                   int32_t chunk) {
+                                                   int32_t chunk, const int32_t *abort) {
+    if (abort && *abort != 0) return;
     __shared__ int32_t sh[2];
     const int lane = lane_id();
     const int64_t lo = (int64_t)blockIdx.x * chunk;
@@ -1228,6 +1241,8 @@ __global__ void k_reset_queue(int32_t *q) { *q = 0; }
 
 // One wave per staged range (grid-stride): pool -> final (a, b, w).
 __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) {
+    if (A.abort && *A.abort != 0) return;
+    if (n_rec < 0) n_rec = min(*A.log_head, A.log_cap);
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -1295,7 +1310,7 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
-                            int32_t *counts) {
+                            int32_t *counts, const int32_t *abort) {
     if (N <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
     const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
@@ -1304,7 +1319,7 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
     k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges, I,
                                                 std::max(1, tu.group_parts), tbase, task_item,
                                                 task_part, small_tasks, small_items, big_tasks,
-                                                counts, chunk);
+                                                counts, chunk, abort);
     return hipGetLastError();
 }
 
@@ -1325,8 +1340,9 @@ hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
 }
 
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &A, int32_t n_rec) {
-    if (n_rec <= 0) return hipSuccess;
-    k_stage_copy<<<grid_for((int64_t)n_rec * kWave, 256, 16384), 256, 0, st>>>(A, n_rec);
+    if (n_rec == 0 || (n_rec < 0 && A.log_cap <= 0)) return hipSuccess;
+    const int64_t most = n_rec < 0 ? A.log_cap : n_rec;
+    k_stage_copy<<<grid_for(most * kWave, 256, 16384), 256, 0, st>>>(A, n_rec);
     return hipGetLastError();
 }
 

@@ -17,6 +17,10 @@ enum : int32_t {
     kErrColRange = 4,     // a member outside [0, n_vertices)
     kErrColOrder = 8,     // a row that is not strictly increasing
     kErrInternal = 16,    // a table probe that found no room (never expected)
+    // a replayed batch plan (fixed buffers): the input or the work outgrew it
+    kErrPlanShape = 32,   // a graph's row_ptr[0] or row_ptr[m] differs from the plan's
+    kErrPlanTasks = 64,   // more counting tasks than the plan's task arrays hold
+    kErrPlanPairs = 128,  // more pairs than the plan's result arrays hold
 };
 
 // Tunable launch parameters of the counting kernels (the autotuner sets them).
@@ -133,11 +137,12 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
                              int32_t *ntask);
 // big_tasks receives, per group of up to group_parts consecutive tasks of an
 // item, the index of the group's first task; counts[1] = number of groups.
+// With `abort` given, the kernel does nothing while *abort != 0.
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
                             int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
-                            int32_t *counts);
+                            int32_t *counts, const int32_t *abort = nullptr);
 
 // Counting-kernel modes.
 enum : int32_t {
@@ -194,9 +199,14 @@ struct CountArgs {
     // [g_ibase[g], g_ibase[g + 1]) and the pairs [g_off[g], g_off[g + 1]); its
     // arrays are g_out[g], g_out[G + g] and g_out[2G + g] (null without
     // weights), and both ids are written less g_ibase[g]
+    // With g_out null, every pair goes to out_a/out_b/out_w at its combined
+    // position, both ids less its graph's g_ibase (g_off unused).
     int32_t n_graphs;
     const int64_t *g_ibase, *g_off;
     int32_t *const *g_out;
+    // Replayed plans: while *abort != 0 the counting and copy kernels do
+    // nothing (the plan's bounds were exceeded, or its input is malformed).
+    const int32_t *abort;
 };
 // `mid` (may be null) is recorded between the one-wave kernel and the task kernel.
 hipError_t launch_count(hipStream_t st, const CountArgs &a, hipEvent_t mid = nullptr);
@@ -225,9 +235,11 @@ hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t 
                             int32_t *item_end, int32_t *err);
 // Combined member lists: zb (G + 1 entries) receives each graph's first
 // combined incidence; memC[ZT] the member ids (one thread per incidence).
+// The concat, length and row kernels do nothing once kErrPlanShape is set in
+// *err (a replayed plan then keeps the lists of its previous run).
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                              int64_t ZT, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *zb, int32_t *memC);
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC, const int32_t *err);
 hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, const int32_t *a,
                                int64_t P, int64_t *off);
 hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,
@@ -236,11 +248,21 @@ hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_
 
 // g_off[g] = task_off of the first task whose item is >= g_ibase[g], for
 // g = 0..G (task_item is non-decreasing; task_off has n_tasks + 1 entries).
+// n_tasks_dev (nullable): the task count on the device, read as
+// min(*n_tasks_dev, n_tasks) (n_tasks is then the task arrays' capacity).
 hipError_t launch_batch_graph_off(hipStream_t st, const int32_t *task_item, int32_t n_tasks,
                                   const int64_t *task_off, const int64_t *g_ibase, int32_t G,
-                                  int64_t *g_off);
+                                  int64_t *g_off, const int64_t *n_tasks_dev = nullptr);
+
+// Replayed plans.  Per graph: row_ptr[0] == 0 and row_ptr[m] == the planned
+// nnz, else kErrPlanShape in *err.  And: *value > cap sets `bit` in *err.
+hipError_t launch_plan_check_shape(hipStream_t st, const BatchGraph *gr, int32_t G, int32_t *err);
+hipError_t launch_plan_guard(hipStream_t st, const int64_t *value, int64_t cap, int32_t bit,
+                             int32_t *err);
 
 // Copy staged ranges to their final place (skipping tasks flagged in need).
+// n_rec < 0: the records are counted on the device (*log_head, at most
+// log_cap), for launches whose sizes are fixed in advance.
 hipError_t launch_stage_copy(hipStream_t st, const CountArgs &a, int32_t n_rec);
 
 // ------------------------------------------------- stages (sline_stages.hip)

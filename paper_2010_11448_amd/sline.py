@@ -123,6 +123,17 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
                                            ctypes.POINTER(sline_edges)]),
+    "sline_batch_plan_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.POINTER(sline_csr),
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_uint32,
+                                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "sline_batch_plan_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(sline_edges)]),
+    "sline_batch_plan_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "sline_batch_plan_destroy": (None, [ctypes.c_void_p]),
     "sline_edges_free": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges)]),
     "sline_filter": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(sline_edges), ctypes.c_int32,
                                       ctypes.c_uint32, ctypes.POINTER(sline_edges)]),
@@ -534,6 +545,81 @@ class Context:
 
 
 # -------------------------------------------------------------- serving
+
+class BatchPlan:
+    """A batch sized once and replayed as one HIP graph launch
+    (sline_batch_plan_* of the C-ABI).
+
+    ``graphs`` are (row_ptr, col, n_vertices) int32 device tensors; they are
+    kept alive with the plan and may be changed in place between runs (same
+    row_ptr[-1]).  ``run`` returns each graph's L_s as views into the plan's
+    result arrays (valid until the next run or ``close``), or copies."""
+
+    def __init__(self, ctx: "Context", graphs, s, dual=None, flags: int = 0):
+        G = len(graphs)
+        self.ctx = ctx
+        self.G = G
+        self.flags = flags
+        self._graphs = list(graphs)
+        dual = [0] * G if dual is None else list(dual)
+        carr = (sline_csr * max(G, 1))(*[Context.csr(rp, col, n) for rp, col, n in graphs])
+        sarr = (ctypes.c_int32 * max(G, 1))(*[int(x) for x in s])
+        darr = (ctypes.c_int32 * max(G, 1))(*[int(x) for x in dual])
+        self.plan = ctypes.c_void_p()
+        st = load().sline_batch_plan_create(ctx.ctx, G, carr, sarr, darr, flags,
+                                            ctypes.byref(self.plan))
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(ctx.ctx))
+        self._outs = (sline_edges * max(G, 1))()
+
+    def info(self) -> tuple[int, int, int]:
+        """(device bytes held, task capacity, pair capacity)."""
+        b, t, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        st = load().sline_batch_plan_info(self.plan, ctypes.byref(b), ctypes.byref(t),
+                                          ctypes.byref(p))
+        if st != SLINE_OK:
+            raise SlineError(st, "sline_batch_plan_info failed")
+        return int(b.value), int(t.value), int(p.value)
+
+    def run_raw(self, s=None) -> int:
+        """One replay; returns the status (results in ``self._outs``)."""
+        sarr = None
+        if s is not None:
+            sarr = (ctypes.c_int32 * max(self.G, 1))(*[int(x) for x in s])
+        return load().sline_batch_plan_run(self.plan, sarr, self._outs)
+
+    def run(self, s=None, copy: bool = False) -> list[LineGraph]:
+        import torch
+        st = self.run_raw(s)
+        if st != SLINE_OK:
+            raise SlineError(st, sline_last_error(self.ctx.ctx))
+        dev = torch.device("cuda", self.ctx.device)
+
+        def col(ptr, n):
+            if not ptr or n == 0:
+                return torch.empty(0, dtype=torch.int32, device=dev)
+            t = torch.as_tensor(_DeviceArray(ptr, n), device=dev)
+            return t.clone() if copy else t
+
+        res = []
+        for g in range(self.G):
+            o = self._outs[g]
+            n = int(o.n_pairs)
+            w = None if (self.flags & SLINE_NO_WEIGHTS) else col(o.w, n)
+            res.append(LineGraph(col(o.a, n), col(o.b, n), w))
+        return res
+
+    def close(self) -> None:
+        if self.plan:
+            load().sline_batch_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class _DeviceArray:
     """Zero-copy view of a device array (int32 by default) for torch.as_tensor."""

@@ -73,6 +73,10 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
         "sline_build_batch": lambda: lib.sline_build_batch(None, 1, None, None, None, 0, None),
         "sline_build_spgemm": lambda: lib.sline_build_spgemm(None, csr, 1, 0, 0,
                                                              ctypes.byref(out)),
+        "sline_batch_plan_create": lambda: lib.sline_batch_plan_create(None, 1, None, None, None, 0,
+                                                                       ctypes.byref(srv)),
+        "sline_batch_plan_run": lambda: lib.sline_batch_plan_run(None, None, None),
+        "sline_batch_plan_info": lambda: lib.sline_batch_plan_info(None, None, None, None),
         "sline_edges_free": lambda: lib.sline_edges_free(None, ctypes.byref(out)),
         "sline_filter": lambda: lib.sline_filter(None, ctypes.byref(out), 1, 0, ctypes.byref(out)),
         "sline_build_sweep": lambda: lib.sline_build_sweep(None, csr, 0, None, 0, 0, None),
@@ -101,6 +105,7 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
     lib.sline_server_destroy(None)
     lib.sline_destroy(None)
     # every declared call is covered here or by a test above
+    lib.sline_batch_plan_destroy(None)
     covered = set(calls) | {"sline_server_last_error", "sline_server_destroy", "sline_destroy",
-                            "sline_last_error", "sline_status_str"}
+                            "sline_last_error", "sline_status_str", "sline_batch_plan_destroy"}
     assert set(declared_functions()) <= covered
