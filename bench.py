@@ -56,6 +56,10 @@ import time
 
 import numpy as np
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+# autotuner cache shipped with the package (entries keyed by workload class)
+TUNE_CACHE = os.path.join(HERE, "paper_2010_11448_amd", "tuning_cache.json")
+
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(ROOT, "paper_2010_11448_amd", "csrc", "sline_count.hip")
@@ -83,6 +87,9 @@ def parse():
                    help="plain/dual forms: take the product route (sline_build_spgemm)")
     p.add_argument("--autotune", action="store_true", help="batch form: tune launch parameters first")
     p.add_argument("--tune-budget", type=float, default=90.0)
+    p.add_argument("--tune-cache", default=TUNE_CACHE,
+                   help="batch form: autotuner cache; its entry for the batch's class is used "
+                        "(with --autotune, the tuned setting is written to it)")
     p.add_argument("--s", default=None, help="comma-separated s values")
     p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -430,11 +437,20 @@ def bench_batch(args, graphs_h, dev, steps, warmup):
             out = ctx.build_owned(rp, col, nv, s, d, flags)
             ctx.free_edges([out])
 
-    tuned = None
+    tuned, source = None, "defaults"
+    sig = autotune.batch_signature(graphs, s_list, dual)
     if args.autotune:
         log("autotuning on the batch")
-        tuned, _ = autotune.tune(ctx, run_batch, budget_s=args.tune_budget,
-                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        tuned, secs = autotune.tune(ctx, run_batch, budget_s=args.tune_budget,
+                                    log=lambda m: print(m, file=sys.stderr, flush=True))
+        source = "autotuned"
+        if args.tune_cache:
+            autotune.save_cached(args.tune_cache, sig, tuned, secs)
+    elif args.tune_cache:
+        entry = autotune.load_cached(args.tune_cache, sig)
+        if entry:
+            ctx.set_tuning(**entry)
+            tuned, source = ctx.tuning(), f"cache {os.path.relpath(args.tune_cache, HERE)}"
     for _ in range(max(warmup, 1)):
         run_batch()
         run_plain()
@@ -490,6 +506,7 @@ def bench_batch(args, graphs_h, dev, steps, warmup):
         "plain_ms_p50": pct([x * 1e3 for x in tp], 50),
         "plain_ms_p99": pct([x * 1e3 for x in tp], 99),
         "steps": steps, "pairs": st["n_pairs"], "tuning": tuned or None,
+        "tuning_source": source, "tuning_class": sig,
         "batched_stage_ms": {k: st[k] for k in ("ms_transpose", "ms_prepare", "ms_count",
                                                 "ms_scan", "ms_fill", "ms_tasks")},
         "task_kernel_GBps": ach,

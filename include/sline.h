@@ -168,7 +168,12 @@ typedef struct {
  *   dense_min_wedges   an item whose candidates give at least this many
  *                      wedges per sub-range narrow enough for direct
  *                      (unhashed) counters is cut into such sub-ranges
- *                      (0..2^24; 0 = sub-ranges by wedge count only) */
+ *                      (0..2^24; 0 = sub-ranges by wedge count only)
+ *   small_slots        home slots of the one-wave kernel's LDS table: 512,
+ *                      1024 or 2048 (small_max_wedges at most half of it)
+ *   task_slots         home slots of the task kernel's LDS table: 4480, 8960
+ *                      (four workgroups per CU) or 13440 (two); larger tables
+ *                      cut fewer sub-ranges per item */
 typedef struct {
     int32_t small_max_wedges;
     int32_t task_wedges;
@@ -178,6 +183,8 @@ typedef struct {
     int32_t task_grid_per_cu;
     int64_t stage_max_bytes;
     int32_t dense_min_wedges;
+    int32_t small_slots;
+    int32_t task_slots;
 } sline_tuning;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`

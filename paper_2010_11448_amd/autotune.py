@@ -2,12 +2,15 @@
 
 The parameters (``sline_tuning``) change speed, never the result: task size
 in wedges, parts per workgroup group, the one-wave / workgroup split, the
-lane-walk threshold and the resident grid sizes.  ``tune`` measures a
+lane-walk threshold, the resident grid sizes and the LDS table sizes of the
+two counting kernels.  ``tune`` measures a
 workload (any callable that runs builds on a Context) under candidate
 settings by coordinate descent -- one parameter at a time, keeping the best
 value before moving to the next -- within a time budget.  Results can be kept
 in a JSON cache keyed by a coarse workload signature, so a later run on a
-workload of the same class starts from the tuned setting.
+workload of the same class uses the tuned setting: ``Context.build_batch``,
+``Context.build_batch_owned`` and ``BatchPlan`` take the cache's path
+(``tuning_cache``) and apply its entry for their batch around the call.
 """
 
 from __future__ import annotations
@@ -21,7 +24,9 @@ from typing import Callable, Iterable
 SPACE: dict[str, list[int]] = {
     "task_wedges": [2500, 3500, 5000, 7000, 10000, 14000],
     "group_parts": [2, 4, 8, 16, 32],
-    "small_max_wedges": [0, 128, 256, 512],
+    "small_slots": [512, 1024, 2048],
+    "task_slots": [4480, 8960, 13440],
+    "small_max_wedges": [0, 128, 256, 512, 1024],
     "light_len": [2, 4, 8, 16],
     "small_grid_per_cu": [4, 8, 16, 32],
     "task_grid_per_cu": [2, 3, 4],
@@ -80,7 +85,13 @@ def tune(ctx, run: Callable[[], None], space: dict[str, list[int]] | None = None
                 if v == best[key]:
                     continue
                 cand = {**best, key: v}
-                ctx.set_tuning(**cand)
+                try:
+                    ctx.set_tuning(**cand)
+                except RuntimeError:
+                    # a combination the library refuses (small_max_wedges
+                    # above half the one-wave table)
+                    ctx.set_tuning(**best)
+                    continue
                 t = _timed(ctx, run, reps)
                 if log:
                     log(f"autotune: {key}={v} {t * 1e3:.1f} ms")
@@ -91,6 +102,36 @@ def tune(ctx, run: Callable[[], None], space: dict[str, list[int]] | None = None
             break
     ctx.set_tuning(**best)
     return best, best_t
+
+
+def batch_signature(graphs, s, dual=None) -> str:
+    """``signature`` of a batch of (row_ptr, col, n_vertices) device tensors
+    (the incidences of a graph are the length of its col)."""
+    nnz = [int(col.numel()) for _, col, _ in graphs]
+    return signature(nnz, s, list(dual) if dual is not None else [0] * len(nnz))
+
+
+class cached_tuning:
+    """Inside the block, ``ctx`` runs with the tuning stored for ``sig`` in the
+    cache file at ``path`` (merged over its own); its own tuning comes back on
+    exit.  No file, no entry or ``path`` None: nothing changes.  The value of
+    the block is the applied entry, or None."""
+
+    def __init__(self, ctx, path: str | None, sig: str):
+        self.ctx, self.path, self.sig = ctx, path, sig
+        self.prev = None
+
+    def __enter__(self):
+        entry = load_cached(self.path, self.sig) if self.path else None
+        if entry:
+            self.prev = self.ctx.tuning()
+            self.ctx.set_tuning(**{**self.prev, **entry})
+        return entry
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            self.ctx.set_tuning(**self.prev)
+        return False
 
 
 def load_cached(path: str, sig: str) -> dict | None:

@@ -2960,13 +2960,19 @@ sline_status sline_get_tuning(sline_ctx *c, sline_tuning *t) {
     t->task_grid_per_cu = c->tune.task_grid_per_cu;
     t->stage_max_bytes = c->tune.stage_max_bytes;
     t->dense_min_wedges = c->tune.dense_min_wedges;
+    t->small_slots = c->tune.small_slots;
+    t->task_slots = c->tune.task_slots;
     return SLINE_OK;
 }
 
 sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     if (!c || !t) return SLINE_EINVAL;
     auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
-    if (!in(t->small_max_wedges, 0, kSmallSlots / 2) || !in(t->task_wedges, 64, 1 << 20) ||
+    const bool slots_ok = (t->small_slots == 512 || t->small_slots == 1024 ||
+                           t->small_slots == 2048) &&
+                          (t->task_slots == 4480 || t->task_slots == 8960 || t->task_slots == 13440);
+    if (!slots_ok || !in(t->small_max_wedges, 0, t->small_slots / 2) ||
+        !in(t->task_wedges, 64, 1 << 20) ||
         !in(t->group_parts, 1, 1024) || !in(t->light_len, 0, 64) ||
         !in(t->small_grid_per_cu, 1, 64) || !in(t->task_grid_per_cu, 1, 16) ||
         t->stage_max_bytes < 0 || !in(t->dense_min_wedges, 0, 1 << 24)) {
@@ -2982,6 +2988,8 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     c->tune.task_grid_per_cu = t->task_grid_per_cu;
     c->tune.stage_max_bytes = t->stage_max_bytes;
     c->tune.dense_min_wedges = t->dense_min_wedges;
+    c->tune.small_slots = t->small_slots;
+    c->tune.task_slots = t->task_slots;
     return SLINE_OK;
 }
 

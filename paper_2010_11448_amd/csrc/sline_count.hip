@@ -995,8 +995,10 @@ __device__ __forceinline__ bool count_idle(const CountArgs &A) {
 
 // --------------------------------------------------------------- small
 
+// SLOTS: home slots of the wave's table (Tuning::small_slots).
+template <int SLOTS>
 __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
-    constexpr int LIM = kSmallSlots + kSmallPad;
+    constexpr int LIM = SLOTS + kSmallPad;
     __shared__ __align__(16) uint32_t tab[LIM + kWave];
     __shared__ int2 runs[kSmallRunCap];
     __shared__ int32_t taken[kSmallRunCap];
@@ -1020,8 +1022,8 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         const int32_t a = A.small_items[r];
         const int64_t c = A.cost[a];
         // 2 W_a home slots (load <= 1/2), rounded up to whole waves
-        int32_t want = (int32_t)std::min<int64_t>(2 * c, kSmallSlots);
-        want = std::min(kSmallSlots, std::max(kWave, ((want + kWave - 1) / kWave) * kWave));
+        int32_t want = (int32_t)std::min<int64_t>(2 * c, SLOTS);
+        want = std::min(SLOTS, std::max(kWave, ((want + kWave - 1) / kWave) * kWave));
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         int32_t cur[kR], end[kR];
         uint32_t lookm;
@@ -1039,9 +1041,13 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
 
 // --------------------------------------------------------------- tasks
 
-__global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
+// SLOTS: home slots of the workgroup's table (Tuning::task_slots); MINB:
+// workgroups per CU the register budget is planned for (the table's LDS
+// allows no more).
+template <int SLOTS, int MINB>
+__global__ __launch_bounds__(kTaskThreads, MINB) void k_count_tasks(CountArgs A) {
     constexpr int NT = kTaskThreads;
-    constexpr int LIM = kTaskSlots + kTaskPad;
+    constexpr int LIM = SLOTS + kTaskPad;
     __shared__ __align__(16) uint32_t tab[LIM + kWave];
     __shared__ int2 runs[kTaskRunCap];
     __shared__ int32_t taken[kTaskRunCap];
@@ -1073,7 +1079,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
         const int32_t P = task_parts(A.cost[a], A.tune.small_max_wedges, A.tune.task_wedges,
                                      item_span(A.item_end, A.N, A.full, a),
                                      A.ptrI[a + 1] - A.ptrI[a], A.tune.dense_min_wedges,
-                                     kTaskSlots);
+                                     SLOTS);
         const int32_t p1 = min(P, p0 + A.tune.group_parts);
         const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
         const int32_t cb = count_bits(k1 - k0);
@@ -1103,7 +1109,7 @@ __global__ __launch_bounds__(kTaskThreads, 4) void k_count_tasks(CountArgs A) {
             }
             fresh = false;
             const int64_t produced = run_range<NT, kTaskPad, kTaskRunCap>(
-                A, S, a, sa, nend, t, lo, hi, kTaskSlots, cb, k0, k1, cur, end, lookm, passes);
+                A, S, a, sa, nend, t, lo, hi, SLOTS, cb, k0, k1, cur, end, lookm, passes);
             if (A.mode != kModeFill && threadIdx.x == 0) {
                 A.task_cnt[t] = (int32_t)produced;
                 my_pairs += produced;
@@ -1140,12 +1146,13 @@ struct PlanItems {
     const int32_t *item_end;  // per item: end of its graph's items (batches), or null
     int32_t full;             // product mode
     int32_t dense_min;        // Tuning::dense_min_wedges
+    int32_t slots;            // Tuning::task_slots
 };
 
 __device__ __forceinline__ int32_t plan_parts(const PlanItems &I, const int64_t *cost, int32_t N,
                                               int32_t small_max, int32_t target, int32_t a) {
     return task_parts(cost[a], small_max, target, item_span(I.item_end, N, I.full, a),
-                      I.ptrI[a + 1] - I.ptrI[a], I.dense_min, kTaskSlots);
+                      I.ptrI[a + 1] - I.ptrI[a], I.dense_min, I.slots);
 }
 
 __global__ void k_task_count(const int64_t *cost, int32_t N, int32_t small_max, int32_t target,
@@ -1300,7 +1307,7 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
                              const int32_t *ptrI, const int32_t *item_end, int32_t full,
                              int32_t *ntask) {
     if (N <= 0) return hipSuccess;
-    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges};
+    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges, tu.task_slots};
     k_task_count<<<grid_for(N, 256, 65536), 256, 0, st>>>(cost, N, tu.small_max_wedges,
                                                          tu.task_wedges, I, ntask);
     return hipGetLastError();
@@ -1315,7 +1322,7 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
     const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
     const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
     const int64_t grid = ((int64_t)N + chunk - 1) / chunk;
-    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges};
+    const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges, tu.task_slots};
     k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges, I,
                                                 std::max(1, tu.group_parts), tbase, task_item,
                                                 task_part, small_tasks, small_items, big_tasks,
@@ -1326,7 +1333,11 @@ hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, cons
 hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
     if (A.N <= 0) return hipSuccess;
     const int gs = std::max(1, A.n_cu * A.tune.small_grid_per_cu);
-    k_count_small<<<gs, kWave, 0, st>>>(A);
+    switch (A.tune.small_slots) {
+    case 512: k_count_small<512><<<gs, kWave, 0, st>>>(A); break;
+    case 2048: k_count_small<2048><<<gs, kWave, 0, st>>>(A); break;
+    default: k_count_small<1024><<<gs, kWave, 0, st>>>(A); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_reset_queue<<<1, 1, 0, st>>>(A.queue);
@@ -1335,7 +1346,11 @@ hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
         if (e != hipSuccess) return e;
     }
     const int gh = std::max(1, A.n_cu * A.tune.task_grid_per_cu);
-    k_count_tasks<<<gh, kTaskThreads, 0, st>>>(A);
+    switch (A.tune.task_slots) {
+    case 4480: k_count_tasks<4480, 4><<<gh, kTaskThreads, 0, st>>>(A); break;
+    case 13440: k_count_tasks<13440, 2><<<gh, kTaskThreads, 0, st>>>(A); break;
+    default: k_count_tasks<8960, 4><<<gh, kTaskThreads, 0, st>>>(A); break;
+    }
     return hipGetLastError();
 }
 

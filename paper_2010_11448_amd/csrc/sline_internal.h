@@ -33,6 +33,8 @@ struct Tuning {
     int32_t task_grid_per_cu = 4;    // resident workgroups per CU for the task kernel
     int64_t stage_max_bytes = 96ll << 30;  // cap of the staging pool (one counting pass)
     int32_t dense_min_wedges = 4096;  // cut items into dense sub-ranges when each gets this many wedges
+    int32_t small_slots = 1024;  // LDS table of the one-wave kernel: 512, 1024 or 2048 home slots
+    int32_t task_slots = 8960;   // LDS table of the task kernel: 4480, 8960 or 13440 home slots
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -40,9 +42,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-// Table sizes (home slots) of the counting kernels.
-constexpr int kSmallSlots = 1024;
-constexpr int kTaskSlots = 8960;  // + 64 pad: 9024 packed 4-byte slots, four workgroups per CU
+// Table sizes (home slots) of the counting kernels are tuning values
+// (Tuning::small_slots, Tuning::task_slots), each kernel built for the sizes
+// listed there: 8960 home slots + 64 pad = 9024 packed 4-byte slots lets four
+// task workgroups share a CU, 13440 two.
 constexpr int kTaskThreads = 256;
 
 // ------------------------------------------------------------ launchers

@@ -69,7 +69,8 @@ class sline_tuning(ctypes.Structure):
     _fields_ = [("small_max_wedges", ctypes.c_int32), ("task_wedges", ctypes.c_int32),
                 ("group_parts", ctypes.c_int32), ("light_len", ctypes.c_int32),
                 ("small_grid_per_cu", ctypes.c_int32), ("task_grid_per_cu", ctypes.c_int32),
-                ("stage_max_bytes", ctypes.c_int64), ("dense_min_wedges", ctypes.c_int32)]
+                ("stage_max_bytes", ctypes.c_int64), ("dense_min_wedges", ctypes.c_int32),
+                ("small_slots", ctypes.c_int32), ("task_slots", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -373,15 +374,26 @@ class Context:
             raise SlineError(st, sline_last_error(self.ctx))
         return out
 
-    def build_batch_owned(self, graphs, s, dual=None, flags: int = 0):
+    def _tuned(self, tuning_cache, graphs, s, dual):
+        """The tuning cached for this batch's class, applied around a call."""
+        from . import autotune
+        if tuning_cache is None:
+            return autotune.cached_tuning(self, None, "")
+        return autotune.cached_tuning(self, tuning_cache,
+                                      autotune.batch_signature(graphs, s, dual))
+
+    def build_batch_owned(self, graphs, s, dual=None, flags: int = 0,
+                          tuning_cache: str | None = None):
         """One sline_build_batch call whose outputs the library allocates
         (capacity 0): returns the ``sline_edges`` array; release every entry
-        with ``free_edges``."""
+        with ``free_edges``.  ``tuning_cache``: an autotuner cache file whose
+        entry for this batch's class applies to the call."""
         G = len(graphs)
         dual = [0] * G if dual is None else list(dual)
         csrs = [self.csr(rp, col, n) for rp, col, n in graphs]
         outs = (sline_edges * max(G, 1))()
-        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        with self._tuned(tuning_cache, graphs, s, dual):
+            st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
         return outs
@@ -391,15 +403,18 @@ class Context:
             sline_edges_free(self.ctx, outs[g])
 
     def build_batch(self, graphs, s, dual=None, flags: int = 0,
-                    library_alloc: bool = False) -> list[LineGraph]:
+                    library_alloc: bool = False,
+                    tuning_cache: str | None = None) -> list[LineGraph]:
         """L_{s[g]} of every graph (row_ptr, col, n_vertices) in one batched call.
 
         library_alloc=True lets the library allocate the outputs (the results
-        are copied into torch tensors and the library's arrays released)."""
+        are copied into torch tensors and the library's arrays released).
+        tuning_cache: an autotuner cache file whose entry for this batch's
+        class applies to the call."""
         import torch
         G = len(graphs)
         if library_alloc:
-            outs = self.build_batch_owned(graphs, s, dual, flags)
+            outs = self.build_batch_owned(graphs, s, dual, flags, tuning_cache)
             dev = torch.device("cuda", self.device)
             nw = bool(flags & SLINE_NO_WEIGHTS)
 
@@ -426,7 +441,8 @@ class Context:
         for g in range(G):
             outs[g] = sline_edges(0, 1, probe[0, g:].data_ptr(), probe[1, g:].data_ptr(),
                                   probe[2, g:].data_ptr())
-        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        with self._tuned(tuning_cache, graphs, s, dual):
+            st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
         if st == SLINE_OK:
             return [LineGraph(probe[0, g:g + int(outs[g].n_pairs)].clone(),
                               probe[1, g:g + int(outs[g].n_pairs)].clone(),
@@ -439,7 +455,8 @@ class Context:
             t = torch.empty((3, max(need[g], 1)), dtype=torch.int32, device=dev)
             bufs.append(t)
             outs[g] = sline_edges(0, max(need[g], 1), t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr())
-        st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
+        with self._tuned(tuning_cache, graphs, s, dual):
+            st = sline_build_batch(self.ctx, csrs, s, dual, flags, outs)
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(self.ctx))
         return [LineGraph(bufs[g][0, :need[g]], bufs[g][1, :need[g]], bufs[g][2, :need[g]])
@@ -552,10 +569,12 @@ class BatchPlan:
 
     ``graphs`` are (row_ptr, col, n_vertices) int32 device tensors; they are
     kept alive with the plan and may be changed in place between runs (same
-    row_ptr[-1]).  ``run`` returns each graph's L_s as views into the plan's
+    row_ptr[-1]).  ``tuning_cache``: an autotuner cache file whose entry for
+    this batch's class the plan is made with.  ``run`` returns each graph's L_s as views into the plan's
     result arrays (valid until the next run or ``close``), or copies."""
 
-    def __init__(self, ctx: "Context", graphs, s, dual=None, flags: int = 0):
+    def __init__(self, ctx: "Context", graphs, s, dual=None, flags: int = 0,
+                 tuning_cache: str | None = None):
         G = len(graphs)
         self.ctx = ctx
         self.G = G
@@ -566,8 +585,10 @@ class BatchPlan:
         sarr = (ctypes.c_int32 * max(G, 1))(*[int(x) for x in s])
         darr = (ctypes.c_int32 * max(G, 1))(*[int(x) for x in dual])
         self.plan = ctypes.c_void_p()
-        st = load().sline_batch_plan_create(ctx.ctx, G, carr, sarr, darr, flags,
-                                            ctypes.byref(self.plan))
+        # the plan keeps the tuning it was created with
+        with ctx._tuned(tuning_cache, graphs, s, dual):
+            st = load().sline_batch_plan_create(ctx.ctx, G, carr, sarr, darr, flags,
+                                                ctypes.byref(self.plan))
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(ctx.ctx))
         self._outs = (sline_edges * max(G, 1))()

@@ -51,3 +51,35 @@ def test_signature_and_cache(tmp_path):
     assert autotune.load_cached(path, sig) is None
     autotune.save_cached(path, sig, {"task_wedges": 7000}, 0.5)
     assert autotune.load_cached(path, sig) == {"task_wedges": 7000}
+
+
+class _Col:
+    def __init__(self, n):
+        self.n = n
+
+    def numel(self):
+        return self.n
+
+
+def test_cached_tuning_applies_and_restores(tmp_path):
+    """The batch path's use of the cache: the entry for the batch's class
+    applies inside the block, the context's own tuning comes back after, and
+    a missing file or entry changes nothing."""
+    ctx = FakeCtx()
+    graphs = [(None, _Col(1000), 5), (None, _Col(3000), 7)]
+    sig = autotune.batch_signature(graphs, [1, 5], [0, 1])
+    assert sig == autotune.signature([1000, 3000], [1, 5], [0, 1])
+    path = str(tmp_path / "tune.json")
+    before = ctx.tuning()
+    with autotune.cached_tuning(ctx, path, sig) as entry:
+        assert entry is None and ctx.tuning() == before
+    autotune.save_cached(path, sig, {"task_wedges": 7000, "group_parts": 16}, 0.5)
+    with autotune.cached_tuning(ctx, path, sig) as entry:
+        assert entry == {"task_wedges": 7000, "group_parts": 16}
+        assert ctx.tuning() == {**before, "task_wedges": 7000, "group_parts": 16}
+    assert ctx.tuning() == before
+    other = autotune.signature([10 ** 8], [1], [0])
+    with autotune.cached_tuning(ctx, path, other) as entry:
+        assert entry is None and ctx.tuning() == before
+    with autotune.cached_tuning(ctx, None, sig) as entry:
+        assert entry is None and ctx.tuning() == before

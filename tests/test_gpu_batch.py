@@ -218,3 +218,32 @@ def test_full_lognormal_batch_every_graph(ctx, dev):
     print(f"case: full lognormal batch: {total} pairs checked in {time.time() - t1:.1f} s",
           flush=True)
     torch.cuda.empty_cache()
+
+
+def test_batch_with_cached_tuning(ctx, dev, tmp_path):
+    """An autotuner cache entry for the batch's class applies to the batched
+    call and to a plan made from it (same results), and the context's own
+    tuning is back afterwards."""
+    from paper_2010_11448_amd import autotune, sline
+
+    graphs, ss, duals = _mixed_batch(16, 23)
+    dg = [to_device(h, dev) for h in graphs]
+    tg = [(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)]
+    path = str(tmp_path / "tune.json")
+    entry = {"small_slots": 2048, "small_max_wedges": 1024, "task_slots": 13440,
+             "task_grid_per_cu": 2, "task_wedges": 3500}
+    autotune.save_cached(path, autotune.batch_signature(tg, ss, duals), entry, 0.1)
+    before = ctx.tuning()
+    print("case: batch with a cached tuning", flush=True)
+    res = ctx.build_batch(tg, ss, duals, tuning_cache=path)
+    assert ctx.tuning() == before
+    plan = sline.BatchPlan(ctx, tg, ss, duals, tuning_cache=path)
+    assert ctx.tuning() == before
+    try:
+        pres = plan.run()
+        for g, (h, s, d) in enumerate(zip(graphs, ss, duals)):
+            ref, _ = oracle.wedge(h.row_ptr, h.col, h.n_edges, h.n_vertices, s, dual=d, threads=8)
+            assert_same(res[g], ref, f"cached tuning graph {g}")
+            assert_same(pres[g], ref, f"cached tuning plan graph {g}")
+    finally:
+        plan.close()

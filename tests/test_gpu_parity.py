@@ -241,7 +241,12 @@ def test_tuning_changes_speed_not_result(ctx, dev):
     variants = [dict(stage_max_bytes=0), dict(stage_max_bytes=1 << 20),
                 dict(task_wedges=64, group_parts=1), dict(task_wedges=20000, group_parts=64),
                 dict(small_max_wedges=0), dict(light_len=0), dict(light_len=64),
-                dict(small_grid_per_cu=1, task_grid_per_cu=1)]
+                dict(small_grid_per_cu=1, task_grid_per_cu=1),
+                # every LDS table size the counting kernels are built for
+                dict(small_slots=512, small_max_wedges=256), dict(small_slots=2048),
+                dict(small_slots=2048, small_max_wedges=1024), dict(task_slots=4480),
+                dict(task_slots=13440, task_grid_per_cu=2),
+                dict(task_slots=4480, dense_min_wedges=0, task_wedges=64)]
     try:
         for v in variants:
             ctx.set_tuning(**{**base, **v})
@@ -257,7 +262,8 @@ def test_tuning_rejects_out_of_range(ctx):
     from paper_2010_11448_amd import sline
     base = ctx.tuning()
     for bad in (dict(task_wedges=1), dict(small_max_wedges=100000), dict(group_parts=0),
-                dict(stage_max_bytes=-1)):
+                dict(stage_max_bytes=-1), dict(small_slots=768), dict(task_slots=9000),
+                dict(small_slots=512, small_max_wedges=512)):
         with pytest.raises(sline.SlineError):
             ctx.set_tuning(**{**base, **bad})
     assert ctx.tuning() == base
