@@ -171,9 +171,10 @@ typedef struct {
  *                      (0..2^24; 0 = sub-ranges by wedge count only)
  *   small_slots        home slots of the one-wave kernel's LDS table: 512,
  *                      1024 or 2048 (small_max_wedges at most half of it)
- *   task_slots         home slots of the task kernel's LDS table: 4480, 8960
- *                      (four workgroups per CU) or 13440 (two); larger tables
- *                      cut fewer sub-ranges per item */
+ *   task_slots         home slots of the task kernel's LDS table: 4480 or 8960
+ *                      (256-thread workgroups, four per CU), 13440 (256
+ *                      threads, two per CU) or 17920 (512 threads, two per
+ *                      CU); larger tables cut fewer sub-ranges per item */
 typedef struct {
     int32_t small_max_wedges;
     int32_t task_wedges;

@@ -25,7 +25,7 @@ SPACE: dict[str, list[int]] = {
     "task_wedges": [2500, 3500, 5000, 7000, 10000, 14000],
     "group_parts": [2, 4, 8, 16, 32],
     "small_slots": [512, 1024, 2048],
-    "task_slots": [4480, 8960, 13440],
+    "task_slots": [4480, 8960, 13440, 17920],
     "small_max_wedges": [0, 128, 256, 512, 1024],
     "light_len": [2, 4, 8, 16],
     "small_grid_per_cu": [4, 8, 16, 32],

@@ -2970,7 +2970,8 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
     const bool slots_ok = (t->small_slots == 512 || t->small_slots == 1024 ||
                            t->small_slots == 2048) &&
-                          (t->task_slots == 4480 || t->task_slots == 8960 || t->task_slots == 13440);
+                          (t->task_slots == 4480 || t->task_slots == 8960 ||
+                           t->task_slots == 13440 || t->task_slots == 17920);
     if (!slots_ok || !in(t->small_max_wedges, 0, t->small_slots / 2) ||
         !in(t->task_wedges, 64, 1 << 20) ||
         !in(t->group_parts, 1, 1024) || !in(t->light_len, 0, 64) ||

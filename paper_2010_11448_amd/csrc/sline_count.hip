@@ -1042,11 +1042,10 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
 // --------------------------------------------------------------- tasks
 
 // SLOTS: home slots of the workgroup's table (Tuning::task_slots); MINB:
-// workgroups per CU the register budget is planned for (the table's LDS
-// allows no more).
-template <int SLOTS, int MINB>
-__global__ __launch_bounds__(kTaskThreads, MINB) void k_count_tasks(CountArgs A) {
-    constexpr int NT = kTaskThreads;
+// waves per SIMD the register budget is planned for (the table's LDS allows
+// no more); NT: threads per workgroup.
+template <int SLOTS, int MINB, int NT>
+__global__ __launch_bounds__(NT, MINB) void k_count_tasks(CountArgs A) {
     constexpr int LIM = SLOTS + kTaskPad;
     __shared__ __align__(16) uint32_t tab[LIM + kWave];
     __shared__ int2 runs[kTaskRunCap];
@@ -1347,9 +1346,12 @@ hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
     }
     const int gh = std::max(1, A.n_cu * A.tune.task_grid_per_cu);
     switch (A.tune.task_slots) {
-    case 4480: k_count_tasks<4480, 4><<<gh, kTaskThreads, 0, st>>>(A); break;
-    case 13440: k_count_tasks<13440, 2><<<gh, kTaskThreads, 0, st>>>(A); break;
-    default: k_count_tasks<8960, 4><<<gh, kTaskThreads, 0, st>>>(A); break;
+    case 4480: k_count_tasks<4480, 4, 256><<<gh, 256, 0, st>>>(A); break;
+    case 13440: k_count_tasks<13440, 2, 256><<<gh, 256, 0, st>>>(A); break;
+    // twice the table and twice the threads: two workgroups per CU keep
+    // four waves per SIMD, as four of 256 threads do
+    case 17920: k_count_tasks<17920, 4, 512><<<gh, 512, 0, st>>>(A); break;
+    default: k_count_tasks<8960, 4, 256><<<gh, 256, 0, st>>>(A); break;
     }
     return hipGetLastError();
 }

@@ -34,7 +34,7 @@ struct Tuning {
     int64_t stage_max_bytes = 96ll << 30;  // cap of the staging pool (one counting pass)
     int32_t dense_min_wedges = 4096;  // cut items into dense sub-ranges when each gets this many wedges
     int32_t small_slots = 1024;  // LDS table of the one-wave kernel: 512, 1024 or 2048 home slots
-    int32_t task_slots = 8960;   // LDS table of the task kernel: 4480, 8960 or 13440 home slots
+    int32_t task_slots = 8960;   // LDS table of the task kernel: 4480, 8960, 13440 or 17920 home slots
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -45,7 +45,8 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 // Table sizes (home slots) of the counting kernels are tuning values
 // (Tuning::small_slots, Tuning::task_slots), each kernel built for the sizes
 // listed there: 8960 home slots + 64 pad = 9024 packed 4-byte slots lets four
-// task workgroups share a CU, 13440 two.
+// 256-thread task workgroups share a CU, 13440 two; 17920 runs with 512
+// threads, two workgroups per CU.
 constexpr int kTaskThreads = 256;
 
 // ------------------------------------------------------------ launchers

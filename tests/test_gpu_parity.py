@@ -246,6 +246,7 @@ def test_tuning_changes_speed_not_result(ctx, dev):
                 dict(small_slots=512, small_max_wedges=256), dict(small_slots=2048),
                 dict(small_slots=2048, small_max_wedges=1024), dict(task_slots=4480),
                 dict(task_slots=13440, task_grid_per_cu=2),
+                dict(task_slots=17920, task_grid_per_cu=2, task_wedges=10000),
                 dict(task_slots=4480, dense_min_wedges=0, task_wedges=64)]
     try:
         for v in variants:
