@@ -174,7 +174,10 @@ typedef struct {
  *   task_slots         home slots of the task kernel's LDS table: 4480 or 8960
  *                      (256-thread workgroups, four per CU), 13440 (256
  *                      threads, two per CU) or 17920 (512 threads, two per
- *                      CU); larger tables cut fewer sub-ranges per item */
+ *                      CU); larger tables cut fewer sub-ranges per item
+ *   tiny_max_wedges    items with a planning cost of at most this (and at most
+ *                      32 members) are counted one per lane, by sorting their
+ *                      candidates (0..10; 0 = off) */
 typedef struct {
     int32_t small_max_wedges;
     int32_t task_wedges;
@@ -186,6 +189,7 @@ typedef struct {
     int32_t dense_min_wedges;
     int32_t small_slots;
     int32_t task_slots;
+    int32_t tiny_max_wedges;
 } sline_tuning;
 
 /* Create a context on HIP device `device` issuing work on `hip_stream`

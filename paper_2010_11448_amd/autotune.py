@@ -26,6 +26,7 @@ SPACE: dict[str, list[int]] = {
     "group_parts": [2, 4, 8, 16, 32],
     "small_slots": [512, 1024, 2048],
     "task_slots": [4480, 8960, 13440, 17920],
+    "tiny_max_wedges": [0, 4, 10],
     "small_max_wedges": [0, 128, 256, 512, 1024],
     "light_len": [2, 4, 8, 16],
     "small_grid_per_cu": [4, 8, 16, 32],

@@ -351,7 +351,7 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
 
 // Task arrays, sized once the task count is known.
 struct TaskLayout {
-    int32_t *item, *part, *small, *small_item, *big, *cnt, *need, *ctrs;
+    int32_t *item, *part, *small, *small_item, *tiny, *tiny_item, *big, *cnt, *need, *ctrs;
     int64_t *off, *part64;
     unsigned long long *pool_head;
     StageRec *log;
@@ -369,6 +369,8 @@ TaskLayout plan_tasks(Arena &A, int64_t T) {
     L.part = A.take<int32_t>(T);
     L.small = A.take<int32_t>(T);
     L.small_item = A.take<int32_t>(T);
+    L.tiny = A.take<int32_t>(T);
+    L.tiny_item = A.take<int32_t>(T);
     L.big = A.take<int32_t>(T);
     L.cnt = A.take<int32_t>(T);
     L.off = A.take<int64_t>(T + 1);
@@ -845,7 +847,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     const TaskLayout TL = plan_tasks(TA, T);
     hip_check(c, launch_task_fill(st, L.cost, (int32_t)N, tu, ptrI, IS.item_end, IS.full ? 1 : 0,
                                   L.tbase, TL.item, TL.part, TL.small,
-                                  TL.small_item, TL.big, L.tcounts),
+                                  TL.small_item, TL.tiny, TL.tiny_item, TL.big, L.tcounts),
               "task fill");
     mark(c, 2);
     // 7. one counting pass: pairs per task, each range's pairs staged in a pool
@@ -880,6 +882,8 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     C.n_tasks = (int32_t)T;
     C.small_tasks = TL.small;
     C.small_items = TL.small_item;
+    C.tiny_tasks = TL.tiny;
+    C.tiny_items = TL.tiny_item;
     C.big_tasks = TL.big;
     C.task_counts = L.tcounts;
     C.queue = L.queue;
@@ -913,18 +917,19 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     hip_check(c, hipMemcpyAsync(h + 4, L.passes, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read passes");
     hip_check(c, hipMemcpyAsync(h + 9, L.passes + 1, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st),
               "read task kernel work");
-    hip_check(c, hipMemcpyAsync(h + 5, L.tcounts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read task counts");
+    hip_check(c, hipMemcpyAsync(h + 12, L.tcounts, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+              "read task counts");
     hip_check(c, hipMemcpyAsync(h + 6, L.err, sizeof(int32_t), hipMemcpyDeviceToHost, st), "read flags");
     hip_check(c, hipMemcpyAsync(h + 7, TL.ctrs, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "read stage counters");
     sync(c, "count pass");
     const int64_t total = h[0];
-    const int32_t *hb = reinterpret_cast<const int32_t *>(h + 5);
+    const int32_t *hb = reinterpret_cast<const int32_t *>(h + 12);
     const int32_t *hc = reinterpret_cast<const int32_t *>(h + 7);
     S.passes = h[4];
     S.heavy_nnz = h[9];
     S.heavy_wedges = h[10];
     S.heavy_pairs = h[11];
-    S.n_small = hb[0];
+    S.n_small = hb[0] + hb[2];  // one-wave and one-lane items
     S.n_heavy = hb[1];
     S.n_pairs = total;
     if (c->profile) {
@@ -1509,7 +1514,8 @@ void plan_enqueue_count(sline_batch_plan *p, hipStream_t st, int64_t pair_cap) {
     const CountArgs &C = p->C;
     const int32_t NI = (int32_t)p->B.NI;
     hip_check(c, launch_task_fill(st, L.cost, NI, C.tune, C.ptrI, p->K.iend, 0, L.tbase, TL.item,
-                                  TL.part, TL.small, TL.small_item, TL.big, L.tcounts, p->d_err),
+                                  TL.part, TL.small, TL.small_item, TL.tiny, TL.tiny_item, TL.big,
+                                  L.tcounts, p->d_err),
               "task fill");
     hip_check(c, launch_fill_i32(st, TL.need, p->t_cap, 0), "zero need flags");
     hip_check(c, launch_fill_i32(st, reinterpret_cast<int32_t *>(TL.log),
@@ -1576,6 +1582,8 @@ CountArgs plan_count_args(sline_batch_plan *p) {
     C.n_tasks = (int32_t)p->t_cap;
     C.small_tasks = TL.small;
     C.small_items = TL.small_item;
+    C.tiny_tasks = TL.tiny;
+    C.tiny_items = TL.tiny_item;
     C.big_tasks = TL.big;
     C.task_counts = L.tcounts;
     C.queue = L.queue;
@@ -2962,6 +2970,7 @@ sline_status sline_get_tuning(sline_ctx *c, sline_tuning *t) {
     t->dense_min_wedges = c->tune.dense_min_wedges;
     t->small_slots = c->tune.small_slots;
     t->task_slots = c->tune.task_slots;
+    t->tiny_max_wedges = c->tune.tiny_max_wedges;
     return SLINE_OK;
 }
 
@@ -2976,7 +2985,8 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
         !in(t->task_wedges, 64, 1 << 20) ||
         !in(t->group_parts, 1, 1024) || !in(t->light_len, 0, 64) ||
         !in(t->small_grid_per_cu, 1, 64) || !in(t->task_grid_per_cu, 1, 16) ||
-        t->stage_max_bytes < 0 || !in(t->dense_min_wedges, 0, 1 << 24)) {
+        t->stage_max_bytes < 0 || !in(t->dense_min_wedges, 0, 1 << 24) ||
+        !in(t->tiny_max_wedges, 0, kTinyMaxCost)) {
         c->last_error = "tuning value out of range";
         return SLINE_EINVAL;
     }
@@ -2991,6 +3001,7 @@ sline_status sline_set_tuning(sline_ctx *c, const sline_tuning *t) {
     c->tune.dense_min_wedges = t->dense_min_wedges;
     c->tune.small_slots = t->small_slots;
     c->tune.task_slots = t->task_slots;
+    c->tune.tiny_max_wedges = t->tiny_max_wedges;
     return SLINE_OK;
 }
 

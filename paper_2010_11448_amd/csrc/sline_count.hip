@@ -587,6 +587,40 @@ __device__ __forceinline__ bool bucket_full(const uint4 &q) {
     return q.x != 0u && q.y != 0u && q.z != 0u && q.w != 0u;
 }
 
+// Stage mode, thread 0 of a workgroup: room for `total` pairs in the pool and
+// `nrec` consecutive log records, taken from this workgroup's chunks (one
+// global atomic per new chunk; records of a chunk left unused stay zero, i.e.
+// empty).  Returns false if the pool or the log has no room left.
+__device__ __forceinline__ bool stage_reserve(const CountArgs &A, uint64_t *pool_cur,
+                                              int32_t *log_cur, int32_t total, int32_t nrec,
+                                              uint64_t &off, int32_t &rec) {
+    off = pool_cur[0];
+    rec = 0;
+    if (off + (uint64_t)total > pool_cur[1]) {
+        const uint64_t size = max((uint64_t)total, (uint64_t)A.pool_chunk);
+        off = atomicAdd(A.pool_head, (unsigned long long)size);
+        if (off + size <= (uint64_t)A.pool_cap) {
+            pool_cur[1] = off + size;
+        } else if (off + (uint64_t)total <= (uint64_t)A.pool_cap) {
+            pool_cur[1] = (uint64_t)A.pool_cap;
+        } else {
+            pool_cur[1] = 0;
+            return false;
+        }
+    }
+    pool_cur[0] = off + (uint64_t)total;
+    if (log_cur[0] + nrec > log_cur[1]) {
+        const int32_t size = max(nrec, A.log_chunk);
+        const int32_t r = atomicAdd(A.log_head, size);
+        log_cur[0] = r;
+        log_cur[1] = (int32_t)min((int64_t)r + size, (int64_t)A.log_cap);
+    }
+    rec = log_cur[0];
+    if (rec + nrec > log_cur[1]) return false;
+    log_cur[0] = rec + nrec;
+    return true;
+}
+
 // Extract the candidates with count >= s and return their number
 // (block-uniform).  Each lane holds one bucket (four slots, one 16-byte LDS
 // read), so the order inside a bucket is settled in registers; only buckets
@@ -649,35 +683,9 @@ __device__ __forceinline__ int32_t tab_extract(const CountArgs &A, const Smem &S
         dst_w = od.w;
     } else if (total && A.mode == kModeStage) {
         if (threadIdx.x == 0) {
-            // Pool room and log slots come from chunks this workgroup reserved
-            // with one global atomic each (records of a chunk left unused stay
-            // zero, i.e. empty).
-            bool ok = true;
-            uint64_t off = S.pool_cur[0];
-            if (off + (uint64_t)total > S.pool_cur[1]) {
-                const uint64_t size = max((uint64_t)total, (uint64_t)A.pool_chunk);
-                off = atomicAdd(A.pool_head, (unsigned long long)size);
-                if (off + size <= (uint64_t)A.pool_cap) {
-                    S.pool_cur[1] = off + size;
-                } else if (off + (uint64_t)total <= (uint64_t)A.pool_cap) {
-                    S.pool_cur[1] = (uint64_t)A.pool_cap;
-                } else {
-                    ok = false;
-                    S.pool_cur[1] = 0;
-                }
-            }
-            int32_t rec = 0;
-            if (ok) {
-                S.pool_cur[0] = off + (uint64_t)total;
-                if (S.log_cur[0] >= S.log_cur[1]) {
-                    const int32_t r = atomicAdd(A.log_head, A.log_chunk);
-                    S.log_cur[0] = r;
-                    S.log_cur[1] = min(r + A.log_chunk, A.log_cap);
-                }
-                rec = S.log_cur[0];
-                ok = rec < S.log_cur[1];
-                if (ok) S.log_cur[0] = rec + 1;
-            }
+            uint64_t off;
+            int32_t rec;
+            const bool ok = stage_reserve(A, S.pool_cur, S.log_cur, total, 1, off, rec);
             if (ok) {
                 StageRec r;
                 r.off = (int64_t)off;
@@ -1039,6 +1047,154 @@ __global__ __launch_bounds__(kWave) void k_count_small(CountArgs A) {
         atomicAdd((unsigned long long *)A.passes, (unsigned long long)passes);
 }
 
+// --------------------------------------------------------------- tiny
+
+// One lane per tiny item: a single-task item with a planning cost of at most
+// Tuning::tiny_max_wedges (so at most kTinyCap wedges, the planning cost
+// being at least a third of them) and at most kTinyCap members, outside
+// product mode.  The lane copies the candidates of all its members' walks
+// into its own column of an LDS buffer, sorts them, and counts each run of
+// equal ids: that count is the overlap.  The candidates come out ascending,
+// in output order.  A workgroup stages the pairs of its 256 items with one
+// reservation.
+__global__ __launch_bounds__(kTinyThreads) void k_count_tiny(CountArgs A) {
+    constexpr int NT = kTinyThreads;
+    __shared__ int32_t buf[kTinyCap * NT];  // column of lane i: buf[q * NT + i]
+    __shared__ int32_t red[2][NT / kWave];
+    __shared__ uint64_t pool_cur[2];
+    __shared__ int32_t log_cur[2];
+    __shared__ int32_t res[4];  // ok, offset low, offset high, first record
+    if (count_idle(A)) return;
+    if (threadIdx.x == 0) {
+        pool_cur[0] = pool_cur[1] = 0;
+        log_cur[0] = log_cur[1] = 0;
+    }
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    int32_t *col = buf + tid;
+    const int32_t n_tiny = A.task_counts[2];
+    __syncthreads();
+    for (int32_t base = blockIdx.x * NT; base < n_tiny; base += gridDim.x * NT) {
+        const int32_t r = base + tid;
+        bool act = r < n_tiny;
+        int32_t t = 0, a = 0, nc = 0, np = 0, sa = 1;
+        if (act) {
+            t = A.tiny_tasks[r];
+            a = A.tiny_items[r];
+            if (A.mode == kModeFill && A.need && !A.need[t]) act = false;
+        }
+        if (act) {
+            sa = A.s_item ? A.s_item[a] : A.s;
+            const int32_t k0 = A.ptrI[a], k1 = A.ptrI[a + 1];
+            for (int32_t k = k0; k < k1; ++k) {
+                const int32_t v = A.memI[k];
+                const int32_t e = A.ptrS[v + 1];
+                for (int32_t p = A.start[k] & kStartMask; p < e; ++p) {
+                    if (nc == kTinyCap) {
+                        atomicOr(A.err, kErrInternal);  // the planning bound was wrong
+                        break;
+                    }
+                    col[nc * NT] = A.itmS[p];
+                    ++nc;
+                }
+            }
+            // insertion sort of the lane's column
+            for (int32_t i = 1; i < nc; ++i) {
+                const int32_t x = col[i * NT];
+                int32_t j = i - 1;
+                while (j >= 0 && col[j * NT] > x) {
+                    col[(j + 1) * NT] = col[j * NT];
+                    --j;
+                }
+                col[(j + 1) * NT] = x;
+            }
+            for (int32_t i = 0; i < nc;) {
+                int32_t j = i + 1;
+                while (j < nc && col[j * NT] == col[i * NT]) ++j;
+                np += (j - i) >= sa;
+                i = j;
+            }
+        }
+        if (act && A.mode != kModeFill) A.task_cnt[t] = np;
+        // where this lane's pairs go
+        int32_t *dst_a = nullptr, *dst_b = nullptr, *dst_w = nullptr;
+        int64_t at = 0;
+        int32_t shift = 0;
+        if (A.mode == kModeFill) {
+            if (act && np) {
+                const OutDst od = out_dst(A, a, A.task_off[t]);
+                dst_a = od.a;
+                dst_b = od.b;
+                dst_w = od.w;
+                at = od.base;
+                shift = od.shift;
+            }
+        } else if (A.mode == kModeStage) {
+            // pairs and records before this lane in the workgroup
+            int32_t pb, pstep;
+            wave_bits_prefix(np, 6, pb, pstep);
+            const uint64_t hm = __ballot(np > 0);
+            if (lane == 0) {
+                red[0][wid] = pstep;
+                red[1][wid] = (int32_t)__popcll(hm);
+            }
+            __syncthreads();
+            int32_t pbefore = pb, rbefore = (int32_t)lanes_below(hm), total = 0, nrec = 0;
+            for (int w = 0; w < NT / kWave; ++w) {
+                if (w < wid) {
+                    pbefore += red[0][w];
+                    rbefore += red[1][w];
+                }
+                total += red[0][w];
+                nrec += red[1][w];
+            }
+            if (tid == 0) {
+                uint64_t off = 0;
+                int32_t rec = 0;
+                const bool ok = total > 0 && stage_reserve(A, pool_cur, log_cur, total, nrec, off, rec);
+                res[0] = ok ? 1 : 0;
+                res[1] = (int32_t)(uint32_t)(off & 0xffffffffull);
+                res[2] = (int32_t)(uint32_t)(off >> 32);
+                res[3] = rec;
+            }
+            __syncthreads();
+            if (act && np) {
+                if (res[0]) {
+                    const int64_t off = (int64_t)(((uint64_t)(uint32_t)res[2] << 32) |
+                                                  (uint64_t)(uint32_t)res[1]);
+                    at = off + pbefore;
+                    dst_b = A.pool_b;
+                    dst_w = A.pool_w;
+                    StageRec rec;
+                    rec.off = at;
+                    rec.t = t;
+                    rec.rel = 0;
+                    rec.n = np;
+                    rec.pad = 0;
+                    A.log[res[3] + rbefore] = rec;
+                } else if (atomicExch(&A.need[t], 1) == 0) {
+                    atomicAdd(A.need_count, 1);  // counted again by the fill pass
+                }
+            }
+            __syncthreads();  // res and red are rewritten by the next round
+        }
+        if (dst_b) {
+            int32_t q = 0;
+            for (int32_t i = 0; i < nc;) {
+                int32_t j = i + 1;
+                const int32_t b = col[i * NT];
+                while (j < nc && col[j * NT] == b) ++j;
+                if (j - i >= sa) {
+                    if (dst_a) dst_a[at + q] = a - shift;
+                    dst_b[at + q] = b - shift;
+                    if (dst_w) dst_w[at + q] = j - i;
+                    ++q;
+                }
+                i = j;
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------------- tasks
 
 // SLOTS: home slots of the workgroup's table (Tuning::task_slots); MINB:
@@ -1168,38 +1324,51 @@ __global__ void k_task_count(const int64_t *cost, int32_t N, int32_t small_max, 
 // with LDS atomics, one per wave and step.
 __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t N,
                                                    int32_t small_max, int32_t target,
-                                                   PlanItems I,
+                                                   int32_t tiny_max, PlanItems I,
                                                    int32_t group, const int64_t *tbase,
                                                    int32_t *task_item, int32_t *task_part,
                                                    int32_t *small_tasks, int32_t *small_items,
+                                                   int32_t *tiny_tasks, int32_t *tiny_items,
                                                    int32_t *groups, int32_t *counts,
                                                    int32_t chunk, const int32_t *abort) {
     if (abort && *abort != 0) return;
-    __shared__ int32_t sh[2];
+    __shared__ int32_t sh[3];
     const int lane = lane_id();
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < N ? lo + chunk : N;
-    if (threadIdx.x == 0) sh[0] = sh[1] = 0;
+    if (threadIdx.x == 0) sh[0] = sh[1] = sh[2] = 0;
     __syncthreads();
+    // a tiny item: one task, a planning cost of at most tiny_max and at most
+    // kTinyCap members, outside product mode (see k_count_tiny)
+    auto is_tiny = [&](int64_t a, int64_t c) {
+        return c <= tiny_max && !I.full && I.ptrI[a + 1] - I.ptrI[a] <= kTinyCap;
+    };
     // pass 1: list entries of the chunk
-    int32_t ns = 0, ng = 0;
+    int32_t ns = 0, ng = 0, nt = 0;
     for (int64_t a = lo + threadIdx.x; a < hi; a += blockDim.x) {
         const int64_t c = cost[a];
         const int32_t P = plan_parts(I, cost, N, small_max, target, (int32_t)a);
         if (P == 0) continue;
-        if (c <= small_max) ++ns;
-        else ng += (P + group - 1) / group;
+        if (c <= small_max) {
+            if (is_tiny(a, c)) ++nt;
+            else ++ns;
+        } else {
+            ng += (P + group - 1) / group;
+        }
     }
     ns = wave_total(ns);
     ng = wave_total(ng);
+    nt = wave_total(nt);
     if (lane == 0) {
         if (ns) atomicAdd(&sh[0], ns);
         if (ng) atomicAdd(&sh[1], ng);
+        if (nt) atomicAdd(&sh[2], nt);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         sh[0] = sh[0] ? atomicAdd(&counts[0], sh[0]) : 0;
         sh[1] = sh[1] ? atomicAdd(&counts[1], sh[1]) : 0;
+        sh[2] = sh[2] ? atomicAdd(&counts[2], sh[2]) : 0;
     }
     __syncthreads();
     // pass 2: tasks, and the list entries at the claimed slots
@@ -1217,16 +1386,25 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
             task_item[t0 + p] = (int32_t)a;
             task_part[t0 + p] = p;
         }
-        const bool small = P > 0 && c <= small_max;
-        const int32_t G = (P > 0 && !small) ? (P + group - 1) / group : 0;
-        const uint64_t sm = __ballot(small);
-        int32_t sbase = 0;
+        const bool one = P > 0 && c <= small_max;
+        const bool tiny = one && is_tiny(a, c);
+        const bool small = one && !tiny;
+        const int32_t G = (P > 0 && !one) ? (P + group - 1) / group : 0;
+        const uint64_t sm = __ballot(small), tm = __ballot(tiny);
+        int32_t sbase = 0, tbase0 = 0;
         if (lane == 0 && sm) sbase = atomicAdd(&sh[0], (int32_t)__popcll(sm));
+        if (lane == 0 && tm) tbase0 = atomicAdd(&sh[2], (int32_t)__popcll(tm));
         sbase = __shfl(sbase, 0, kWave);
+        tbase0 = __shfl(tbase0, 0, kWave);
         if (small) {
             const int32_t q = sbase + (int32_t)lanes_below(sm);
             small_tasks[q] = (int32_t)t0;
             small_items[q] = (int32_t)a;
+        }
+        if (tiny) {
+            const int32_t q = tbase0 + (int32_t)lanes_below(tm);
+            tiny_tasks[q] = (int32_t)t0;
+            tiny_items[q] = (int32_t)a;
         }
         int32_t incl = G;  // inclusive prefix of G over the wave
 #pragma unroll
@@ -1315,22 +1493,30 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
-                            int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
-                            int32_t *counts, const int32_t *abort) {
+                            int32_t *small_tasks, int32_t *small_items, int32_t *tiny_tasks,
+                            int32_t *tiny_items, int32_t *big_tasks, int32_t *counts,
+                            const int32_t *abort) {
     if (N <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>(1024, ((int64_t)N + 255) / 256);
     const int32_t chunk = (int32_t)((((int64_t)N + blocks - 1) / blocks + 255) / 256 * 256);
     const int64_t grid = ((int64_t)N + chunk - 1) / chunk;
     const PlanItems I{ptrI, item_end, full, tu.dense_min_wedges, tu.task_slots};
-    k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges, I,
+    k_task_fill<<<(unsigned)grid, 256, 0, st>>>(cost, N, tu.small_max_wedges, tu.task_wedges,
+                                                tu.tiny_max_wedges, I,
                                                 std::max(1, tu.group_parts), tbase, task_item,
-                                                task_part, small_tasks, small_items, big_tasks,
-                                                counts, chunk, abort);
+                                                task_part, small_tasks, small_items, tiny_tasks,
+                                                tiny_items, big_tasks, counts, chunk, abort);
     return hipGetLastError();
 }
 
 hipError_t launch_count(hipStream_t st, const CountArgs &A, hipEvent_t mid) {
     if (A.N <= 0) return hipSuccess;
+    if (A.tune.tiny_max_wedges > 0 && !A.full) {
+        // LDS (the 32 KB candidate buffer) allows four workgroups per CU
+        k_count_tiny<<<std::max(1, A.n_cu * 4), kTinyThreads, 0, st>>>(A);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const int gs = std::max(1, A.n_cu * A.tune.small_grid_per_cu);
     switch (A.tune.small_slots) {
     case 512: k_count_small<512><<<gs, kWave, 0, st>>>(A); break;

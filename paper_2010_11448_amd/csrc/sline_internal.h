@@ -35,6 +35,7 @@ struct Tuning {
     int32_t dense_min_wedges = 4096;  // cut items into dense sub-ranges when each gets this many wedges
     int32_t small_slots = 1024;  // LDS table of the one-wave kernel: 512, 1024 or 2048 home slots
     int32_t task_slots = 8960;   // LDS table of the task kernel: 4480, 8960, 13440 or 17920 home slots
+    int32_t tiny_max_wedges = 10;  // one-task items up to this planning cost go one per lane (0: off)
 };
 
 // Scan tile: 256 threads x 8 items.
@@ -48,6 +49,13 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 // 256-thread task workgroups share a CU, 13440 two; 17920 runs with 512
 // threads, two workgroups per CU.
 constexpr int kTaskThreads = 256;
+// Tiny items (one lane each): at most kTinyCap members and kTinyCap wedges.
+// The planning cost is at least a third of the wedges (lookup-only members
+// lower it no further), so tiny_max_wedges <= kTinyMaxCost keeps every
+// tiny item's wedges within kTinyCap.
+constexpr int kTinyCap = 32;
+constexpr int kTinyMaxCost = 10;
+constexpr int kTinyThreads = 256;
 
 // ------------------------------------------------------------ launchers
 // Every launcher enqueues on `st` and returns the launch status.
@@ -142,11 +150,14 @@ hipError_t launch_task_count(hipStream_t st, const int64_t *cost, int32_t N, con
 // big_tasks receives, per group of up to group_parts consecutive tasks of an
 // item, the index of the group's first task; counts[1] = number of groups.
 // With `abort` given, the kernel does nothing while *abort != 0.
+// Tiny one-task items (Tuning::tiny_max_wedges) go to tiny_tasks /
+// tiny_items instead of the small lists; counts[2] receives their number.
 hipError_t launch_task_fill(hipStream_t st, const int64_t *cost, int32_t N, const Tuning &tu,
                             const int32_t *ptrI, const int32_t *item_end, int32_t full,
                             const int64_t *tbase, int32_t *task_item, int32_t *task_part,
-                            int32_t *small_tasks, int32_t *small_items, int32_t *big_tasks,
-                            int32_t *counts, const int32_t *abort = nullptr);
+                            int32_t *small_tasks, int32_t *small_items, int32_t *tiny_tasks,
+                            int32_t *tiny_items, int32_t *big_tasks, int32_t *counts,
+                            const int32_t *abort = nullptr);
 
 // Counting-kernel modes.
 enum : int32_t {
@@ -176,7 +187,8 @@ struct CountArgs {
     int32_t n_tasks;
     const int32_t *small_tasks, *big_tasks;
     const int32_t *small_items;  // item of each small task
-    const int32_t *task_counts;  // [0] small tasks, [1] task groups
+    const int32_t *tiny_tasks, *tiny_items;  // tiny tasks (one lane each) and their items
+    const int32_t *task_counts;  // [0] small tasks, [1] task groups, [2] tiny tasks
     int32_t *queue;              // big-task queue head (reset by the launcher)
     int32_t *task_cnt;           // count mode: pairs per task
     const int64_t *task_off;     // fill mode: output offset per task (nullptr = count mode)

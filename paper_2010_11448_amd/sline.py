@@ -70,7 +70,8 @@ class sline_tuning(ctypes.Structure):
                 ("group_parts", ctypes.c_int32), ("light_len", ctypes.c_int32),
                 ("small_grid_per_cu", ctypes.c_int32), ("task_grid_per_cu", ctypes.c_int32),
                 ("stage_max_bytes", ctypes.c_int64), ("dense_min_wedges", ctypes.c_int32),
-                ("small_slots", ctypes.c_int32), ("task_slots", ctypes.c_int32)]
+                ("small_slots", ctypes.c_int32), ("task_slots", ctypes.c_int32),
+                ("tiny_max_wedges", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -247,7 +247,9 @@ def test_tuning_changes_speed_not_result(ctx, dev):
                 dict(small_slots=2048, small_max_wedges=1024), dict(task_slots=4480),
                 dict(task_slots=13440, task_grid_per_cu=2),
                 dict(task_slots=17920, task_grid_per_cu=2, task_wedges=10000),
-                dict(task_slots=4480, dense_min_wedges=0, task_wedges=64)]
+                dict(task_slots=4480, dense_min_wedges=0, task_wedges=64),
+                # items counted one per lane: off, and with a small pool
+                dict(tiny_max_wedges=0), dict(tiny_max_wedges=4, stage_max_bytes=1 << 20)]
     try:
         for v in variants:
             ctx.set_tuning(**{**base, **v})
@@ -264,7 +266,7 @@ def test_tuning_rejects_out_of_range(ctx):
     base = ctx.tuning()
     for bad in (dict(task_wedges=1), dict(small_max_wedges=100000), dict(group_parts=0),
                 dict(stage_max_bytes=-1), dict(small_slots=768), dict(task_slots=9000),
-                dict(small_slots=512, small_max_wedges=512)):
+                dict(small_slots=512, small_max_wedges=512), dict(tiny_max_wedges=11)):
         with pytest.raises(sline.SlineError):
             ctx.set_tuning(**{**base, **bad})
     assert ctx.tuning() == base
