@@ -175,9 +175,10 @@ typedef struct {
  *                      (256-thread workgroups, four per CU), 13440 (256
  *                      threads, two per CU) or 17920 (512 threads, two per
  *                      CU); larger tables cut fewer sub-ranges per item
- *   tiny_max_wedges    items with a planning cost of at most this (and at most
- *                      32 members) are counted one per lane, by sorting their
- *                      candidates (0..10; 0 = off) */
+ *   tiny_max_wedges    in builds of at least 32768 items, items with a
+ *                      planning cost of at most this (and at most 32 members)
+ *                      are counted one per lane, by sorting their candidates
+ *                      (0..10; 0 = off) */
 typedef struct {
     int32_t small_max_wedges;
     int32_t task_wedges;

@@ -317,6 +317,16 @@ struct Layout {
     int32_t *part32, *ntask, *start;
 };
 
+// The tuning one build runs with: one lane per tiny item pays off only when
+// the items outnumber the lanes of the resident one-wave workgroups several
+// times over (a lane walks its item's lists one entry after another).
+constexpr int64_t kTinyMinItems = 1 << 15;
+Tuning build_tuning(const Tuning &t, int64_t n_items) {
+    Tuning u = t;
+    if (n_items < kTinyMinItems) u.tiny_max_wedges = 0;
+    return u;
+}
+
 Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64_t M, bool filt) {
     Layout L{};
     L.err = A.take<int32_t>(4);
@@ -795,7 +805,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
         itmS = L.itmS;
     }
     // 6. wedge counts, tasks
-    const Tuning tu = c->tune;
+    const Tuning tu = build_tuning(c->tune, N);
     if (!filt && !IS.full)
         hip_check(c, launch_start_from_map(st, nnz, map, L.start), "back-pointers");
     // degree-based pruning (Sec. IV-C) unless switched off: items smaller
@@ -1738,6 +1748,7 @@ sline_status plan_create_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, cons
     const sline_status rb = batch_bases(c, p->gr, nnz, p->B);
     if (rb != SLINE_OK) return rb;
     const BatchBases &B = p->B;
+    p->C.tune = build_tuning(c->tune, B.NI);
     if (G > 0) {
         hip_check(c, hipMemcpyAsync(p->d_gr, p->gr.data(), sizeof(BatchGraph) * G,
                                     hipMemcpyHostToDevice, st),

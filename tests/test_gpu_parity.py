@@ -261,6 +261,25 @@ def test_tuning_changes_speed_not_result(ctx, dev):
         ctx.set_tuning(**base)
 
 
+@pytest.mark.parametrize("tiny", [10, 4, 0])
+def test_tiny_items_one_per_lane(ctx, dev, tiny):
+    """Builds with enough items (>= 32768) count their tiny items one per lane;
+    the result equals the oracle with that path at two cost limits and off."""
+    g = gen.uniform_hypergraph(50_000, 60_000, 2, 9, seed=31)
+    rp, col = to_device(g, dev)
+    base = ctx.tuning()
+    ctx.set_tuning(**{**base, "tiny_max_wedges": tiny})
+    try:
+        for dual, s in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3)):
+            print(f"case: tiny={tiny} s={s} dual={dual}", flush=True)
+            L = ctx.build(rp, col, g.n_vertices, s, dual)
+            ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual,
+                                  threads=8)
+            assert_same(L, ref, f"tiny={tiny} s={s} dual={dual}")
+    finally:
+        ctx.set_tuning(**base)
+
+
 def test_tuning_rejects_out_of_range(ctx):
     from paper_2010_11448_amd import sline
     base = ctx.tuning()
