@@ -343,7 +343,7 @@ Layout plan_layout(Arena &A, int64_t m, int64_t n, int64_t nnz, int64_t N, int64
     L.rsK1 = A.take<int32_t>(nnz);
     L.rsV0 = A.take<int32_t>(nnz);
     L.rsV1 = A.take<int32_t>(nnz);
-    L.rsHist = A.take<int32_t>(16 * transpose_tiles(nnz) + 1);
+    L.rsHist = A.take<int32_t>(transpose_hist(nnz));
     const int64_t pmax = scan_partials(std::max<int64_t>({n, N, M, m, nnz}) + 1);
     L.part32 = A.take<int32_t>(pmax);
     L.part64 = A.take<int64_t>(pmax);
@@ -1160,7 +1160,7 @@ Combine plan_combine(Arena &A, const BatchBases &B) {
     K.X.rsK1 = A.take<int32_t>(B.ZD);
     K.X.rsV0 = A.take<int32_t>(B.ZD);
     K.X.rsV1 = A.take<int32_t>(B.ZD);
-    K.X.rsHist = A.take<int32_t>(16 * transpose_tiles(B.ZD) + 1);
+    K.X.rsHist = A.take<int32_t>(transpose_hist(B.ZD));
     K.X.part32 = A.take<int32_t>(scan_partials(std::max<int64_t>({B.VD, B.NI, B.ZD}) + 1));
     K.len = A.take<int32_t>(B.NI);
     K.ptrC = A.take<int32_t>(B.NI + 1);
@@ -2167,10 +2167,10 @@ SortBufs plan_sort(Arena &A, int64_t n, int64_t nk) {
     B.rsK[1] = A.take<int32_t>(n);
     B.rsV[0] = A.take<int32_t>(n);
     B.rsV[1] = A.take<int32_t>(n);
-    B.hist = A.take<int32_t>(16 * transpose_tiles(n) + 1);
+    B.hist = A.take<int32_t>(transpose_hist(n));
     // partials of the digit scans, and of scans over n or nk entries
     B.part32 = A.take<int32_t>(
-        scan_partials(std::max<int64_t>({16 * transpose_tiles(n), nk, n}) + 1));
+        scan_partials(std::max<int64_t>({transpose_hist(n), nk, n}) + 1));
     B.ptrT = A.take<int32_t>(nk + 1);
     return B;
 }

@@ -84,9 +84,10 @@ hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map
 // kT[q] = the incidence at transposed slot q and posT[k] = its slot (kT,
 // posT may be null).  A stable least-significant-digit radix sort of the
 // (member, incidence) pairs; rsK / rsV are two pairs of nnz-entry buffers,
-// hist holds 16 * transpose_tiles(nnz) + 1 counts and part32 the partials of
-// their scan.
+// hist holds transpose_hist(nnz) counts and part32 the partials of their
+// scan.
 int64_t transpose_tiles(int64_t nnz);
+int64_t transpose_hist(int64_t nnz);
 // Radix passes of a transpose over members in [0, n); its sorted members end
 // in rsK[(passes - 1) & 1].
 int transpose_passes(int32_t n);

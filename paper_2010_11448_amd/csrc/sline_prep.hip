@@ -683,6 +683,8 @@ hipError_t launch_start_from_map(hipStream_t st, int64_t nnz, const int32_t *map
 
 int64_t transpose_tiles(int64_t nnz) { return (nnz + kRsTile - 1) / kRsTile; }
 
+int64_t transpose_hist(int64_t nnz) { return (int64_t)kRsBins * transpose_tiles(nnz) + 1; }
+
 int transpose_passes(int32_t n) {
     int bits = 0;
     while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
