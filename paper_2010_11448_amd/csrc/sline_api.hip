@@ -1361,8 +1361,9 @@ sline_status batch_impl(sline_ctx *c, int32_t G, const sline_csr *Hs, const int3
             c->direct.G = G;
             c->direct.outs = outs;
         }
-        const sline_status r =
-            build_core(c, CH, s_min, 0, flags | SLINE_SKIP_VALIDATE, &comb, IS);
+        // the combined lists' row check verifies the member order of every
+        // primal graph (SLINE_SKIP_VALIDATE, if given, skips it)
+        const sline_status r = build_core(c, CH, s_min, 0, flags, &comb, IS);
         if (r == SLINE_OK && c->direct.done) {
             release_pool(c);
             dev_free(c, big, big_bytes);
@@ -1489,7 +1490,9 @@ void plan_enqueue_prep(sline_batch_plan *p, hipStream_t st, int64_t t_cap) {
     hip_check(c, launch_fill_i32(st, L.tcounts, 4, 0), "zero task counts");
     hip_check(c, launch_fill_i64(st, L.totals, 4, 0), "zero totals");
     hip_check(c, launch_fill_i64(st, L.passes, 4, 0), "zero passes");
-    hip_check(c, launch_rows(st, ptrI, memI, NI, MT, B.ZT, 0, L.rowid, L.err), "row ids");
+    // row ids, and the member order of every row (a primal graph's combined
+    // ids keep its members' order); a violation stops the run's counting
+    hip_check(c, launch_rows(st, ptrI, memI, NI, MT, B.ZT, 1, L.rowid, p->d_err), "row ids");
     int32_t *const rk[2] = {L.rsK0, L.rsK1};
     int32_t *const rv[2] = {L.rsV0, L.rsV1};
     hip_check(c, launch_transpose(st, memI, B.ZT, MT, L.rowid, rk, rv, L.rsHist, L.part32, L.ptrT,
@@ -1916,12 +1919,13 @@ sline_status plan_run_impl(sline_batch_plan *p, const int32_t *s, sline_edges *o
     }
     sync(c, "batch plan run");
     const int32_t e = reinterpret_cast<const int32_t *>(w)[0];
-    if (e & (kErrPlanTasks | kErrPlanPairs)) {
+    // a malformed input first: its counts mean nothing
+    if (e & ~(kErrPlanTasks | kErrPlanPairs)) return plan_csr_error(c, e);
+    if (e) {
         set_err(c, "batch plan: the run needs more %s than the plan holds; make a new plan",
                 (e & kErrPlanTasks) ? "counting tasks" : "pairs");
         return SLINE_ECAPACITY;
     }
-    if (e) return plan_csr_error(c, e);
     if (reinterpret_cast<const int32_t *>(w + 1)[0] & kErrInternal) {
         set_err(c, "internal error: counting table overflow");
         return SLINE_EDEVICE;

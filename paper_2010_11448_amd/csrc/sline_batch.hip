@@ -109,17 +109,10 @@ __global__ void k_batch_len(const BatchGraph *gr, const int64_t *ibase, int32_t 
             if (b < 0 || en < b || en > d.nnz) {
                 atomicOr(err, kErrRowPtrOrder);
                 l = 0;
-            } else {
-                // members in range and strictly increasing
-                int32_t bad = 0, prev = -1;
-                for (int32_t k = b; k < en; ++k) {
-                    const int32_t v = d.col[k];
-                    if (v < 0 || v >= d.n) bad |= kErrColRange;
-                    if (v <= prev) bad |= kErrColOrder;
-                    prev = v;
-                }
-                if (bad) atomicOr(err, bad);
             }
+            // members: the range is checked per incidence by k_batch_rows,
+            // the order within each row on the combined lists (the combined
+            // member ids of a primal graph keep its members' order)
         }
         len[i] = l;
         s_item[i] = d.s;
@@ -140,7 +133,7 @@ __global__ void k_batch_zbase(const int64_t *ibase, int32_t G, const int32_t *pt
 // vertices), whose entries are combined row ids of XD turned into member ids.
 __global__ void k_batch_rows(const BatchGraph *gr, const int32_t *zb, int32_t G, int64_t ZT,
                              const int32_t *ptrT, const int32_t *colT, int32_t *memC,
-                             const int32_t *err) {
+                             int32_t *err) {
     if (*err & kErrPlanShape) return;
     for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < ZT;
          z += (int64_t)gridDim.x * blockDim.x) {
@@ -155,9 +148,12 @@ __global__ void k_batch_rows(const BatchGraph *gr, const int32_t *zb, int32_t G,
         if (d.dual) {
             memC[z] = (int32_t)(colT[ptrT[d.vdbase] + k] - d.dbase + d.mbase);
         } else {
-            // a malformed graph (reported by k_batch_len) may map past its col
+            // a graph with bad row bounds (reported by k_batch_len) may map
+            // past its col
             const int32_t v = k < d.nnz ? d.col[k] : -1;
-            memC[z] = (v >= 0 && v < d.n) ? (int32_t)(d.mbase + v) : (int32_t)d.mbase;
+            const bool in = v >= 0 && v < d.n;
+            if (!in && k < d.nnz) atomicOr(err, kErrColRange);
+            memC[z] = in ? (int32_t)(d.mbase + v) : (int32_t)d.mbase;
         }
     }
 }
@@ -278,7 +274,7 @@ hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t 
 
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                              int64_t ZT, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *zb, int32_t *memC, const int32_t *err) {
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC, int32_t *err) {
     if (G <= 0) return hipSuccess;
     k_batch_zbase<<<grid_for((int64_t)G + 1, 256), 256, 0, st>>>(ibase, G, ptrC, zb);
     hipError_t e = hipGetLastError();

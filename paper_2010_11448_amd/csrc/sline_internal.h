@@ -251,12 +251,14 @@ hipError_t launch_batch_len(hipStream_t st, const BatchGraph *gr, const int64_t 
                             int64_t NI, const int32_t *ptrT, int32_t *len, int32_t *s_item,
                             int32_t *item_end, int32_t *err);
 // Combined member lists: zb (G + 1 entries) receives each graph's first
-// combined incidence; memC[ZT] the member ids (one thread per incidence).
+// combined incidence; memC[ZT] the member ids (one thread per incidence),
+// members out of range reported in *err (kErrColRange).  The order of the
+// members within a row is left to the row check of the combined lists.
 // The concat, length and row kernels do nothing once kErrPlanShape is set in
 // *err (a replayed plan then keeps the lists of its previous run).
 hipError_t launch_batch_rows(hipStream_t st, const BatchGraph *gr, const int64_t *ibase, int32_t G,
                              int64_t ZT, const int32_t *ptrT, const int32_t *colT,
-                             const int32_t *ptrC, int32_t *zb, int32_t *memC, const int32_t *err);
+                             const int32_t *ptrC, int32_t *zb, int32_t *memC, int32_t *err);
 hipError_t launch_batch_bounds(hipStream_t st, const int64_t *ibase, int32_t G, const int32_t *a,
                                int64_t P, int64_t *off);
 hipError_t launch_batch_split(hipStream_t st, const int64_t *ibase, const int64_t *off, int32_t G,

@@ -164,6 +164,12 @@ def test_plan_rejects_malformed_and_outgrown_runs(ctx, dev):
         assert plan.run_raw() == sline.SLINE_EINVAL
         col0.copy_(keep)
         _check(plan.run(), graphs, ss, duals, "restored after a bad member")
+        # a member twice in one row
+        col0[1] = col0[0]
+        print("case: plan run with a row out of order", flush=True)
+        assert plan.run_raw() == sline.SLINE_EINVAL
+        col0.copy_(keep)
+        _check(plan.run(), graphs, ss, duals, "restored after a row out of order")
         # row_ptr[m] changed
         rp_keep = rp0.clone()
         rp0[-1] = rp0[-1] - 1
