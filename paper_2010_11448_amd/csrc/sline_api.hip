@@ -831,7 +831,7 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     }
     if (!(flags & SLINE_NO_SHORTCUT))
         hip_check(c, launch_mark_lookup(st, ptrI, memI, (int32_t)N, s, IS.s_item, IS.s_max, ptrS,
-                                        L.start, L.cost),
+                                        L.start, L.cost, IS.full ? 0 : tu.tiny_max_wedges),
                   "lookup members");
     hip_check(c, launch_task_count(st, L.cost, (int32_t)N, tu, ptrI, IS.item_end, IS.full ? 1 : 0,
                                    L.ntask),
@@ -1507,10 +1507,10 @@ void plan_enqueue_prep(sline_batch_plan *p, hipStream_t st, int64_t t_cap) {
     hip_check(c, launch_cost(st, ptrI, memI, NI, p->s_min, p->K.s_item, L.ptrS, L.itmS, L.cost,
                              L.start, L.totals, 0, 1),
               "cost");
-    hip_check(c, launch_mark_lookup(st, ptrI, memI, NI, p->s_min, p->K.s_item, INT32_MAX, L.ptrS,
-                                    L.start, L.cost),
-              "lookup members");
     const Tuning &tu = p->C.tune;
+    hip_check(c, launch_mark_lookup(st, ptrI, memI, NI, p->s_min, p->K.s_item, INT32_MAX, L.ptrS,
+                                    L.start, L.cost, tu.tiny_max_wedges),
+              "lookup members");
     hip_check(c, launch_task_count(st, L.cost, NI, tu, ptrI, p->K.iend, 0, L.ntask), "task count");
     hip_check(c, launch_scan_i32_to_i64(st, L.ntask, NI, L.tbase, L.part64), "task scan");
     if (t_cap >= 0)

@@ -136,9 +136,12 @@ hipError_t launch_product_filter(hipStream_t st, const int32_t *a, const int32_t
 constexpr int32_t kStartMask = 0x7fffffff;
 constexpr int32_t kMaxLookup = 15;  // lookup-only members per item at most
 // s_item (nullable) gives each item its own s (batches); s_max is the largest.
+// Items with at most kTinyCap members and at most tiny_max wedges (0: none)
+// are left as they are: the one-lane path counts every wedge of them.
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                               int32_t s, const int32_t *s_item, int32_t s_max,
-                              const int32_t *ptrS, int32_t *start, int64_t *cost);
+                              const int32_t *ptrS, int32_t *start, int64_t *cost,
+                              int32_t tiny_max);
 
 // Tasks: item a with W_a wedges becomes P_a tasks (equal sub-ranges of its
 // candidate range); ntask[a] = P_a.  Task t of item a (t = tbase[a] + p) is

@@ -497,11 +497,15 @@ template <int W>
 __global__ __launch_bounds__(256) void k_mark_lookup(const int32_t *ptrI, const int32_t *memI,
                                                      int32_t N, int32_t s_all,
                                                      const int32_t *s_item, const int32_t *ptrS,
-                                                     int32_t *start, int64_t *cost) {
+                                                     int32_t *start, int64_t *cost,
+                                                     int32_t tiny_max) {
     for_rows<W, kGroup * kKeysPerLane>(ptrI, N, [&](int64_t a, int gl) {
         const int32_t b = ptrI[a], e = ptrI[a + 1];
         const int32_t s = s_item ? s_item[a] : s_all;
         if (e - b < s) return;
+        // a tiny item by its exact wedges stays tiny: it is counted one per
+        // lane, every wedge, so lookup-only members would change nothing
+        if (e - b <= kTinyCap && cost[a] <= tiny_max) return;
         const int32_t rounds = min(min(s - 1, kMaxLookup), e - b - 1);
         int64_t flagged = 0;
         if (e - b <= W * kKeysPerLane) {
@@ -753,14 +757,15 @@ hipError_t launch_cost(hipStream_t st, const int32_t *ptrI, const int32_t *memI,
 
 hipError_t launch_mark_lookup(hipStream_t st, const int32_t *ptrI, const int32_t *memI, int32_t N,
                               int32_t s, const int32_t *s_item, int32_t s_max,
-                              const int32_t *ptrS, int32_t *start, int64_t *cost) {
+                              const int32_t *ptrS, int32_t *start, int64_t *cost,
+                              int32_t tiny_max) {
     if (N <= 0 || s_max <= 1) return hipSuccess;
     k_mark_lookup<kGroup><<<grid_for((int64_t)N * kGroup, 256, 65536), 256, 0, st>>>(
-        ptrI, memI, N, s, s_item, ptrS, start, cost);
+        ptrI, memI, N, s, s_item, ptrS, start, cost, tiny_max);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_mark_lookup<kWave><<<grid_for(N, 256, 4096), 256, 0, st>>>(
-        ptrI, memI, N, s, s_item, ptrS, start, cost);
+        ptrI, memI, N, s, s_item, ptrS, start, cost, tiny_max);
     return hipGetLastError();
 }
 
