@@ -423,9 +423,9 @@ void worker_loop(sline_server *S, int wi) {
                     const bool alone = S->in_flight == 0 && batch.empty() && reuse.empty();
                     const bool fits = S->in_flight + S->held + est + qe <= S->budget;
                     if (!alone && !fits) break;
-                    // a build above the whole budget runs alone, with all the
-                    // device memory the kept results would hold
-                    if (!fits && !can_reuse) evict_kept(S, 0);
+                    // a build above the whole budget runs alone; kept results
+                    // stay unless it runs out of device memory (then they go
+                    // and it is tried again)
                     est += qe;
                     if (can_reuse) {
                         kt->second.users += 1;
