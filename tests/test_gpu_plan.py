@@ -254,3 +254,29 @@ def test_plan_of_law_graphs(ctx, dev):
         _check(plan.run(), graphs, ss, duals, "law batch")
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_plan_randomized(ctx, dev, seed):
+    """Random batches (random sets, sizes, sides, per-graph s) replayed at the
+    planned s and at random larger s, every graph against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    G = int(rng.integers(1, 12))
+    graphs, ss, duals = [], [], []
+    for g in range(G):
+        m, n = int(rng.integers(0, 120)), int(rng.integers(1, 90))
+        p = float(rng.uniform(0.02, 0.4))
+        B = rng.random((m, n)) < p
+        graphs.append(gen.from_sets([np.flatnonzero(B[i]).tolist() for i in range(m)], n))
+        ss.append(int(rng.integers(1, 5)))
+        duals.append(int(rng.integers(0, 2)))
+    dg = [to_device(h, dev) for h in graphs]
+    print(f"case: plan randomized seed={seed} G={G} s={ss} dual={duals}", flush=True)
+    plan = _plan(ctx, dg, graphs, ss, duals)
+    try:
+        _check(plan.run(), graphs, ss, duals, f"seed {seed} planned s")
+        for r in range(3):
+            s2 = [s + int(rng.integers(0, 4)) for s in ss]
+            _check(plan.run(s2), graphs, s2, duals, f"seed {seed} run {r} s={s2}")
+    finally:
+        plan.close()
