@@ -541,7 +541,7 @@ def bench_serve(args, catalog, dev):
     qs = gen.serving_arrivals(ns, nl, rate=args.rate, duration_s=args.duration)
     srv = sline.Server(0, hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_batch=64,
                        workers=args.workers)
-    srv.set_reuse(int(args.reuse_gb * (1 << 30)), REUSE_MIN_NNZ)
+    srv.set_reuse(int(args.reuse_gb * (1 << 30)), REUSE_MIN_NNZ, lookahead=True)
     ids = [srv.register(rp, col, n) for rp, col, n in dgr]
     # warm the server: a few queries, and the largest result of each large
     # graph (maps the device memory its cache will reuse)
@@ -602,7 +602,7 @@ def bench_serve(args, catalog, dev):
     srv.set_reuse(0)
     t_sat_plain_server = saturate()
     log("saturation with result reuse")
-    srv.set_reuse(int(args.reuse_gb * (1 << 30)), REUSE_MIN_NNZ)
+    srv.set_reuse(int(args.reuse_gb * (1 << 30)), REUSE_MIN_NNZ, lookahead=True)
     r0 = srv.reuse_stats()
     t_sat = saturate()
     r1 = srv.reuse_stats()
@@ -657,6 +657,7 @@ def bench_serve(args, catalog, dev):
         "served_vs_plain_no_reuse": t_plain / t_sat_plain_server,
         "slowest": slow,
         "reuse": {"cache_bytes": int(args.reuse_gb * (1 << 30)), "min_nnz": REUSE_MIN_NNZ,
+                  "lookahead": True,
                   "arrival_run_reused": reuse_arrival["reused"],
                   "saturation_reused": r1["reused"] - r0["reused"],
                   "saturation_kept": r1["kept"] - r0["kept"]},

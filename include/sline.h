@@ -461,8 +461,16 @@ sline_status sline_server_release(sline_server *srv, sline_edges *out);
  * that graph and side with s >= the kept s is answered by sline_filter from
  * it instead of a build; the answer is the same.  cache_bytes = 0 turns
  * reuse off and drops what is kept.  Defaults: a quarter of the budget (at
- * most 32 GiB), min_nnz = 2^20. */
-sline_status sline_server_set_reuse(sline_server *srv, int64_t cache_bytes, int64_t min_nnz);
+ * most 32 GiB), min_nnz = 2^20, no flags.
+ * flags: SLINE_REUSE_LOOKAHEAD -- a query of s > 2 that must build looks at
+ * the queued queries of its graph and side and builds at the smallest s
+ * (>= 2) among them; its own answer is that build filtered to its s, and the
+ * others wait for the build and are answered from the kept result.  It pays
+ * when cache_bytes holds one result per graph and side in use; with less,
+ * the larger builds are evicted before they are reused. */
+#define SLINE_REUSE_LOOKAHEAD 1u
+sline_status sline_server_set_reuse(sline_server *srv, int64_t cache_bytes, int64_t min_nnz,
+                                    uint32_t flags);
 
 /* Queries answered by reuse, results kept so far, and bytes kept now (any
  * pointer may be NULL). */

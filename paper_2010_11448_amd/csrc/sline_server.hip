@@ -239,6 +239,7 @@ void cache_free(void *p, size_t n, void *stream, void *user) {
 struct Query {
     int64_t ticket = 0;
     int32_t graph = 0, s = 1, dual = 0;
+    int32_t s_build = 1;  // s its build runs at (<= s; below s, filtered to s after)
     int64_t est = 0;
     bool reused = false;  // answered by filtering a kept result
     sline_query_info info{};
@@ -294,6 +295,7 @@ struct sline_server {
     int64_t kept_bytes = 0;
     int64_t reuse_cap = 0;      // bytes the kept results may hold (0: no reuse)
     int64_t reuse_min_nnz = 0;  // graphs with fewer incidences are not kept
+    bool lookahead = false;     // SLINE_REUSE_LOOKAHEAD
     int64_t use_clock = 0;
     int64_t n_reused = 0, n_kept = 0;  // queries answered by a filter, results kept
 };
@@ -383,6 +385,8 @@ int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual)
     return (int64_t)(80.0 * (double)g.nnz + 20.0 * pairs) + (1 << 20);
 }
 
+void free_arrays(sline_server *S, const sline_edges &e);
+
 void worker_loop(sline_server *S, int wi) {
     sline_server::Worker &W = S->workers[wi];
     (void)hipSetDevice(S->device);
@@ -413,9 +417,25 @@ void worker_loop(sline_server *S, int wi) {
                             continue;
                         }
                     }
+                    // Queued queries of the same graph and side that a kept
+                    // result could answer: one build at the smallest s (>= 2)
+                    // among them answers them all -- this one by a filter of
+                    // the build, the others from the kept result -- where
+                    // each would otherwise build in turn.
+                    int32_t s_build = q.s;
+                    if (S->lookahead && !can_reuse && S->reuse_cap > 0 && q.s > 2 &&
+                        S->graphs[q.graph].nnz >= S->reuse_min_nnz) {
+                        for (const int64_t t2 : S->queue) {
+                            const Query &o = S->queries[t2];
+                            if (o.graph == q.graph && o.dual == q.dual && o.s >= 2 && o.s < s_build)
+                                s_build = o.s;
+                        }
+                    }
                     // a filtered result is at most the kept one
                     const int64_t qe =
-                        can_reuse ? kt->second.bytes + ((int64_t)1 << 20) : q.est;
+                        can_reuse ? kt->second.bytes + ((int64_t)1 << 20)
+                        : s_build == q.s ? q.est
+                                         : estimate(S, S->graphs[q.graph], s_build, q.dual);
                     // results the client has not released count against the
                     // budget too (so a slow client holds back admission); kept
                     // results live beside the budget, within their own cap,
@@ -435,9 +455,10 @@ void worker_loop(sline_server *S, int wi) {
                         from.push_back(kt->second.e);
                         from_key.push_back(kt->first);
                     } else {
+                        q.s_build = s_build;
                         batch.push_back(q.ticket);
                         auto bt = S->building.find(key);
-                        if (bt == S->building.end() || bt->second > q.s) S->building[key] = q.s;
+                        if (bt == S->building.end() || bt->second > s_build) S->building[key] = s_build;
                     }
                     qi = S->queue.erase(qi);
                 }
@@ -450,7 +471,7 @@ void worker_loop(sline_server *S, int wi) {
         const int32_t G = (int32_t)batch.size();
         const int32_t R = (int32_t)reuse.size();
         std::vector<sline_csr> Hs(G);
-        std::vector<int32_t> ss(G), ds(G), gs(G), rs(R);
+        std::vector<int32_t> ss(G), ds(G), gs(G), want(G), rs(R);
         std::vector<sline_edges> outs(G), routs(R);
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -458,7 +479,8 @@ void worker_loop(sline_server *S, int wi) {
             for (int32_t g = 0; g < G; ++g) {
                 Query &q = S->queries[batch[g]];
                 Hs[g] = S->graphs[q.graph].H;
-                ss[g] = q.s;
+                ss[g] = q.s_build;
+                want[g] = q.s;
                 ds[g] = q.dual;
                 gs[g] = q.graph;
                 outs[g] = sline_edges{};
@@ -572,10 +594,30 @@ void worker_loop(sline_server *S, int wi) {
                 auto bt = S->building.find({gs[g], ds[g]});
                 if (bt != S->building.end() && bt->second == ss[g]) S->building.erase(bt);
             }
+        }
+        // queries built at a smaller s than they asked for: their answer is
+        // the build filtered to their s (the build itself stays only as a
+        // kept result, if it was kept)
+        std::vector<sline_edges> fouts(G);
+        for (int32_t g = 0; g < G; ++g) {
+            if (qst[g] != SLINE_OK || want[g] == ss[g]) continue;
+            fouts[g] = sline_edges{};
+            const sline_status fs = sline_filter(W.ctx, &outs[g], want[g], 0, &fouts[g]);
+            if (fs != SLINE_OK) err = sline_last_error(W.ctx);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                free_arrays(S, outs[g]);
+            }
+            outs[g] = fouts[g];
+            qst[g] = fs;
+            if (fs != SLINE_OK && st == SLINE_OK) st = fs;
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
             for (int32_t g = 0; g < G; ++g) {
                 Query &q = S->queries[batch[g]];
                 q.info.status = qst[g];
-                q.info.t_done_ns = t_done;
+                q.info.t_done_ns = now_ns();
                 if (qst[g] == SLINE_OK) {
                     q.out = outs[g];
                     q.info.n_pairs = outs[g].n_pairs;
@@ -721,6 +763,7 @@ sline_status sline_server_submit(sline_server *S, int32_t graph_id, int32_t s, i
         q.s = s;
         q.dual = dual;
         q.est = estimate(S, S->graphs[graph_id], s, dual);
+        q.s_build = s;
         q.info.t_submit_ns = now_ns();
         q.info.status = SLINE_EBUSY;
         *ticket = q.ticket;
@@ -761,12 +804,15 @@ sline_status sline_server_release(sline_server *S, sline_edges *out) {
     return SLINE_OK;
 }
 
-sline_status sline_server_set_reuse(sline_server *S, int64_t cache_bytes, int64_t min_nnz) {
-    if (!S || cache_bytes < 0 || min_nnz < 0) return SLINE_EINVAL;
+sline_status sline_server_set_reuse(sline_server *S, int64_t cache_bytes, int64_t min_nnz,
+                                    uint32_t flags) {
+    if (!S || cache_bytes < 0 || min_nnz < 0 || (flags & ~(uint32_t)SLINE_REUSE_LOOKAHEAD))
+        return SLINE_EINVAL;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->reuse_cap = cache_bytes;
         S->reuse_min_nnz = min_nnz;
+        S->lookahead = (flags & SLINE_REUSE_LOOKAHEAD) != 0;
         evict_kept(S, cache_bytes);
     }
     // map room for the budget and the kept results up front (if the device

@@ -27,6 +27,7 @@ SLINE_EBUSY = -5
 SLINE_SKIP_VALIDATE = 1
 SLINE_PROFILE = 2
 SLINE_NO_WEIGHTS = 4
+SLINE_REUSE_LOOKAHEAD = 1
 SLINE_RELABEL_DESC = 8
 SLINE_RELABEL_ASC = 16
 SLINE_NO_PRUNE = 32
@@ -165,7 +166,8 @@ SIGNATURES = {
     "sline_server_pending": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int32)]),
     "sline_server_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
-    "sline_server_set_reuse": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
+    "sline_server_set_reuse": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_uint32]),
     "sline_server_reuse_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                                   ctypes.POINTER(ctypes.c_int64),
                                                   ctypes.POINTER(ctypes.c_int64)]),
@@ -681,9 +683,11 @@ class Server:
             raise SlineError(st, "sline_server_submit failed")
         return int(t.value)
 
-    def set_reuse(self, cache_bytes: int, min_nnz: int = 0) -> None:
-        """Result reuse (sline_server_set_reuse); cache_bytes = 0 turns it off."""
-        st = load().sline_server_set_reuse(self.srv, int(cache_bytes), int(min_nnz))
+    def set_reuse(self, cache_bytes: int, min_nnz: int = 0, lookahead: bool = False) -> None:
+        """Result reuse (sline_server_set_reuse); cache_bytes = 0 turns it off;
+        lookahead sets SLINE_REUSE_LOOKAHEAD."""
+        st = load().sline_server_set_reuse(self.srv, int(cache_bytes), int(min_nnz),
+                                           SLINE_REUSE_LOOKAHEAD if lookahead else 0)
         if st != SLINE_OK:
             raise SlineError(st, "sline_server_set_reuse failed")
 

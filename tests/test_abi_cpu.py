@@ -93,7 +93,7 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
         "sline_server_poll": lambda: lib.sline_server_poll(None, 0, ctypes.byref(out), None),
         "sline_server_release": lambda: lib.sline_server_release(None, ctypes.byref(out)),
         "sline_server_pending": lambda: lib.sline_server_pending(None, None, None),
-        "sline_server_set_reuse": lambda: lib.sline_server_set_reuse(None, 0, 0),
+        "sline_server_set_reuse": lambda: lib.sline_server_set_reuse(None, 0, 0, 0),
         "sline_server_reuse_stats": lambda: lib.sline_server_reuse_stats(None, None, None, None),
     }
     for name, call in calls.items():

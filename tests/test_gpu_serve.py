@@ -50,7 +50,8 @@ def _drain(srv, tickets, timeout_s=120.0):
 
 
 @pytest.mark.parametrize("workers,budget,reuse", [(2, 64 << 30, False), (1, 1 << 20, False),
-                                                  (2, 64 << 30, True), (3, 8 << 30, True)])
+                                                  (2, 64 << 30, True), (3, 8 << 30, True),
+                                                  (3, 64 << 30, "lookahead")])
 def test_mixed_queries_equal_alone(dev, workers, budget, reuse):
     from paper_2010_11448_amd import sline
 
@@ -58,8 +59,9 @@ def test_mixed_queries_equal_alone(dev, workers, budget, reuse):
     dg = [to_device(h, dev) for h in graphs]
     srv = sline.Server(0, hbm_budget_bytes=budget, max_batch=16, workers=workers)
     # reuse on every graph (kept results answer later queries by a filter),
-    # or none at all
-    srv.set_reuse(1 << 30 if reuse else 0, 0)
+    # with queued queries of one graph and side built once at their smallest
+    # s (lookahead), or none at all
+    srv.set_reuse(1 << 30 if reuse else 0, 0, lookahead=reuse == "lookahead")
     ctx = sline.Context(0)
     try:
         ids = [srv.register(rp, col, h.n_vertices) for (rp, col), h in zip(dg, graphs)]
