@@ -465,9 +465,11 @@ sline_status sline_server_release(sline_server *srv, sline_edges *out);
  * flags: SLINE_REUSE_LOOKAHEAD -- a query of s > 2 that must build looks at
  * the queued queries of its graph and side and builds at the smallest s
  * (>= 2) among them; its own answer is that build filtered to its s, and the
- * others wait for the build and are answered from the kept result.  It pays
- * when cache_bytes holds one result per graph and side in use; with less,
- * the larger builds are evicted before they are reused. */
+ * others wait for the build and are answered from the kept result.  Queued
+ * queries that a kept result answers are then admitted before the others
+ * (each is one filter), while their result is still kept.  It pays when
+ * cache_bytes holds a result for the graphs and sides in use; with less, the
+ * larger builds are evicted before they are reused. */
 #define SLINE_REUSE_LOOKAHEAD 1u
 sline_status sline_server_set_reuse(sline_server *srv, int64_t cache_bytes, int64_t min_nnz,
                                     uint32_t flags);

@@ -400,6 +400,33 @@ void worker_loop(sline_server *S, int wi) {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
                 if (S->stop) return;
+                // queries a kept result answers go first, wherever they are
+                // in the queue: each is one filter, and answering them while
+                // their result is kept spares a rebuild once it is evicted
+                if (S->lookahead && !S->kept.empty()) {
+                    for (auto qi = S->queue.begin();
+                         qi != S->queue.end() && (int32_t)reuse.size() < S->max_batch;) {
+                        Query &q = S->queries[*qi];
+                        const std::pair<int32_t, int32_t> key{q.graph, q.dual};
+                        auto kt = S->kept.find(key);
+                        if (kt == S->kept.end() || kt->second.s > q.s) {
+                            ++qi;
+                            continue;
+                        }
+                        const int64_t qe = kt->second.bytes + ((int64_t)1 << 20);
+                        const bool alone = S->in_flight == 0 && reuse.empty();
+                        if (!alone && S->in_flight + S->held + est + qe > S->budget) break;
+                        est += qe;
+                        kt->second.users += 1;
+                        kt->second.last = ++S->use_clock;
+                        q.reused = true;
+                        reuse.push_back(q.ticket);
+                        from.push_back(kt->second.e);
+                        from_key.push_back(kt->first);
+                        qi = S->queue.erase(qi);
+                    }
+                    if (!reuse.empty()) break;
+                }
                 // admit in arrival order while the batch and the budget allow;
                 // a query larger than the budget runs alone when nothing else does
                 for (auto qi = S->queue.begin();
