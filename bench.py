@@ -75,7 +75,7 @@ def parse():
                    choices=["plain", "dual", "batch", "serve", "stages", "copy", "cpu"])
     p.add_argument("--plain-only", action="store_true",
                    help="plain form: skip the uniform, batch and serve sub-objects")
-    p.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
+    p.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     p.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     p.add_argument("--catalog-small", type=int, default=1024)
     p.add_argument("--catalog-large", type=int, default=8)
