@@ -33,7 +33,8 @@ def test_readme_example():
     col = ns["col"].cpu().numpy()
     ref, _ = oracle.naive(rp, col, len(rp) - 1, 5, 2, dual=1)
     assert_same(ns["D"], ref, "README dual s=2")
-    for got, s in zip(ns["outs"], (1, 2)):
+    for got, plan_got, s in zip(ns["outs"], ns["P"], (1, 2)):
         ref, _ = oracle.naive(rp, col, len(rp) - 1, 5, s)
         assert_same(got, ref, f"README batch s={s}")
+        assert_same(plan_got, ref, f"README plan s={s}")
     assert np.array_equal(ns["L"].w.cpu().numpy(), [2, 2])
