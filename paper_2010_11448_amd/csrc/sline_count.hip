@@ -1424,18 +1424,51 @@ __global__ __launch_bounds__(256) void k_task_fill(const int64_t *cost, int32_t 
 __global__ void k_reset_queue(int32_t *q) { *q = 0; }
 
 // One wave per staged range (grid-stride): pool -> final (a, b, w).
+// A record as the stage pass wrote it, checked all the same: it guards the
+// indices the copy uses.
+__device__ __forceinline__ bool stage_rec_ok(const CountArgs &A, const StageRec &rec) {
+    return rec.t >= 0 && rec.t < A.n_tasks && rec.n >= 0 && rec.off >= 0 &&
+           rec.off + rec.n <= A.pool_cap;
+}
+
+// Records of at most this many pairs are copied by one lane each (a task of a
+// tiny or small item stages a handful of pairs); longer ones by a whole wave.
+constexpr int32_t kLaneRec = 32;
+
 __global__ __launch_bounds__(256) void k_stage_copy(CountArgs A, int32_t n_rec) {
     if (A.abort && *A.abort != 0) return;
     if (n_rec < 0) n_rec = min(*A.log_head, A.log_cap);
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    // short records: one lane each
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rec;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const StageRec rec = A.log[r];
+        if (rec.n > kLaneRec) continue;  // a wave's, below
+        if (!stage_rec_ok(A, rec)) {
+            atomicOr(A.err, kErrInternal);
+            continue;
+        }
+        if (rec.n == 0 || A.need[rec.t]) continue;
+        const int32_t a = A.task_item[rec.t];
+        const int64_t dst = A.task_off[rec.t] + rec.rel;
+        if (rec.rel < 0 || dst + rec.n > A.task_off[rec.t + 1]) {
+            atomicOr(A.err, kErrInternal);
+            continue;
+        }
+        const OutDst od = out_dst(A, a, dst);
+        for (int32_t i = 0; i < rec.n; ++i) {
+            od.a[od.base + i] = a - od.shift;
+            od.b[od.base + i] = A.pool_b[rec.off + i] - od.shift;
+            if (od.w) od.w[od.base + i] = A.pool_w[rec.off + i];
+        }
+    }
+    // long records: one wave each
     for (int64_t r = wave; r < n_rec; r += nwaves) {
         const StageRec rec = A.log[r];
-        // every record was written by the stage pass; the checks guard the
-        // indices below all the same
-        if (rec.t < 0 || rec.t >= A.n_tasks || rec.n < 0 || rec.off < 0 ||
-            rec.off + rec.n > A.pool_cap) {
+        if (rec.n <= kLaneRec) continue;  // copied above
+        if (!stage_rec_ok(A, rec)) {
             if (lane == 0) atomicOr(A.err, kErrInternal);
             continue;
         }
