@@ -798,8 +798,10 @@ sline_status build_core(sline_ctx *c, const sline_csr &H, int32_t s, int32_t dua
     // 5. s filter
     const int32_t *ptrS = ptrM, *itmS = itmM;
     if (filt) {
-        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, nnz, ptrI, s, IS.s_item, L.pos,
-                                   L.part32, L.ptrS, L.itmS, inv, L.start),
+        // the task counts are written later: until then their array holds
+        // the filter's per-item keep flags
+        hip_check(c, launch_filter(st, ptrM, itmM, (int32_t)M, nnz, ptrI, (int32_t)N, s, IS.s_item,
+                                   L.ntask, L.pos, L.part32, L.ptrS, L.itmS, inv, L.start),
                   "filter");
         ptrS = L.ptrS;
         itmS = L.itmS;
@@ -1501,8 +1503,8 @@ void plan_enqueue_prep(sline_batch_plan *p, hipStream_t st, int64_t t_cap) {
     // every item carries its graph's s; the filter, the costs and the
     // lookup-only members read them per item, so a run's s need not be the
     // planned one
-    hip_check(c, launch_filter(st, L.ptrT, L.colT, MT, B.ZT, ptrI, p->s_min, p->K.s_item, L.pos,
-                               L.part32, L.ptrS, L.itmS, L.kT, L.start),
+    hip_check(c, launch_filter(st, L.ptrT, L.colT, MT, B.ZT, ptrI, NI, p->s_min, p->K.s_item,
+                               L.ntask, L.pos, L.part32, L.ptrS, L.itmS, L.kT, L.start),
               "filter");
     hip_check(c, launch_cost(st, ptrI, memI, NI, p->s_min, p->K.s_item, L.ptrS, L.itmS, L.cost,
                              L.start, L.totals, 0, 1),

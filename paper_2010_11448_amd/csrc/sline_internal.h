@@ -103,10 +103,11 @@ hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int
 // With start given, the back-pointer of every kept entry is written as well:
 // start[inv[p]] = (its position in itmS) + 1, inv mapping member-list
 // positions to item incidences.
+// kept (N entries, scratch) receives each item's keep flag first.
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         int64_t nnz, const int32_t *ptrI, int32_t s, const int32_t *s_item,
-                         int32_t *pos, int32_t *part32, int32_t *ptrS, int32_t *itmS,
-                         const int32_t *inv, int32_t *start);
+                         int64_t nnz, const int32_t *ptrI, int32_t N, int32_t s,
+                         const int32_t *s_item, int32_t *kept, int32_t *pos, int32_t *part32,
+                         int32_t *ptrS, int32_t *itmS, const int32_t *inv, int32_t *start);
 
 // Per-item exact wedge count W_a, the back-pointer start[k] (first item > a
 // in N_s(v) for member incidence k of a kept item a) and the run totals:

@@ -394,15 +394,21 @@ __global__ void k_rs_bounds(const int32_t *sk, int64_t nnz, int32_t n, int32_t *
 // The s filter as a stream compaction: the filtered lists N_s(v), one after
 // the other, are the kept entries of the member lists in their order, so the
 // position of a kept entry is the number of kept entries before it.
-// keep[p] = 1 if entry p of the member lists is an item with |S| >= s
-// (s_item[it] for item it when given).
-__global__ void k_filter_flags(const int32_t *itmM, int64_t nnz, const int32_t *ptrI, int32_t s,
-                               const int32_t *s_item, int32_t *keep) {
+// kept[it] = 1 if item it has |S| >= s (s_item[it] when given); then
+// keep[p] = kept[itmM[p]] for entry p of the member lists (one gather per
+// entry instead of the item's two list bounds and its s).
+__global__ void k_item_kept(const int32_t *ptrI, int32_t N, int32_t s, const int32_t *s_item,
+                            int32_t *kept) {
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < N;
+         it += (int64_t)gridDim.x * blockDim.x)
+        kept[it] = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s) ? 1 : 0;
+}
+
+__global__ void k_filter_flags(const int32_t *itmM, int64_t nnz, const int32_t *kept,
+                               int32_t *keep) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t it = itmM[p];
-        keep[p] = (ptrI[it + 1] - ptrI[it]) >= (s_item ? s_item[it] : s) ? 1 : 0;
-    }
+         p += (int64_t)gridDim.x * blockDim.x)
+        keep[p] = kept[itmM[p]];
 }
 
 // After the exclusive scan of the flags (pos[p], pos[nnz] = kept total): kept
@@ -724,12 +730,13 @@ hipError_t launch_transpose(hipStream_t st, const int32_t *col, int64_t nnz, int
 }
 
 hipError_t launch_filter(hipStream_t st, const int32_t *ptrM, const int32_t *itmM, int32_t M,
-                         int64_t nnz, const int32_t *ptrI, int32_t s, const int32_t *s_item,
-                         int32_t *pos, int32_t *part32, int32_t *ptrS, int32_t *itmS,
-                         const int32_t *inv, int32_t *start) {
+                         int64_t nnz, const int32_t *ptrI, int32_t N, int32_t s,
+                         const int32_t *s_item, int32_t *kept, int32_t *pos, int32_t *part32,
+                         int32_t *ptrS, int32_t *itmS, const int32_t *inv, int32_t *start) {
     if (M <= 0) return hipSuccess;
     if (nnz > 0) {
-        k_filter_flags<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(itmM, nnz, ptrI, s, s_item, pos);
+        k_item_kept<<<grid_for(N, 256, 65536), 256, 0, st>>>(ptrI, N, s, s_item, kept);
+        k_filter_flags<<<grid_for(nnz, 256, 65536), 256, 0, st>>>(itmM, nnz, kept, pos);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
