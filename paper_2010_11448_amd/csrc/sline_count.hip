@@ -411,8 +411,11 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
                     }
                     sl = s0 | (K << 16);
                 } else {
-                    // no room: blank the slots this reservation holds, walk by lane
-                    for (int32_t k = s0; k < min(s0 + K, RUNCAP); ++k) S.runs[k] = make_int2(0, 0);
+                    // no room: blank the slots this reservation holds, walk by
+                    // lane.  A blank piece is empty and its clamped index
+                    // (end - 1) lies in the member's own run.
+                    for (int32_t k = s0; k < min(s0 + K, RUNCAP); ++k)
+                        S.runs[k] = make_int2(end[i], end[i]);
                 }
             }
             if (sl < 0) light |= 1u << i;
@@ -472,7 +475,9 @@ __device__ __forceinline__ void insert_range(const CountArgs &A, const Smem &S, 
         for (int k = 0; k < 4; ++k) {
             j[k] = INT32_MAX;
             if (pr[k] >= 0) {
-                // pp < pe while the piece is open: the clamped index is in it
+                // the clamped index lies in the piece's member run: pe - 1 is
+                // its last entry, also for empty pieces (blank, or planned
+                // past the run's end), which read it and count nothing
                 const int32_t v = A.itmS[min(pp[k] + lane, pe[k] - 1)];
                 if (pp[k] + lane < pe[k]) j[k] = v;
             }

@@ -261,6 +261,51 @@ def test_tuning_changes_speed_not_result(ctx, dev):
         ctx.set_tuning(**base)
 
 
+def _claim_graph(seed: int = 5):
+    """Hyperedges 0..9 each hold vertices 0..399, which lie in 240, 410 and 8
+    other hyperedges (150, 150 and 100 of them); 6000 more vertices lie in one
+    random hyperedge each (4000 hyperedges)."""
+    rng = np.random.default_rng(seed)
+    m, core = 4000, 400
+    deg = np.concatenate([np.full(150, 240), np.full(150, 410), np.full(100, 8)])
+    rows = [np.repeat(np.arange(10, dtype=np.int64), core)]
+    cols = [np.tile(np.arange(core, dtype=np.int64), 10)]
+    for v in range(core):
+        rows.append(rng.choice(np.arange(10, m), size=int(deg[v]), replace=False))
+        cols.append(np.full(int(deg[v]), v, np.int64))
+    rows.append(rng.integers(10, m, size=6000))
+    cols.append(np.arange(core, core + 6000, dtype=np.int64))
+    key = np.unique(np.concatenate(rows) * 10 ** 6 + np.concatenate(cols))
+    r, c = key // 10 ** 6, key % 10 ** 6
+    rp = np.zeros(m + 1, np.int64)
+    np.add.at(rp, r + 1, 1)
+    return gen.Hypergraph(np.cumsum(rp).astype(np.int32), c.astype(np.int32), m, core + 6000,
+                          dict(kind="claims"))
+
+
+@pytest.mark.parametrize("tune", [dict(light_len=0, task_wedges=1 << 20), dict(light_len=0),
+                                  dict()])
+def test_piece_claims_past_capacity(ctx, dev, tune):
+    """Ten items of 400 members whose runs ask for one to three pieces each
+    (about 850 in all when the item is one task): more than a workgroup's
+    run arrays hold, so reservations fail, one of them part-way through the
+    arrays (its slots are left as empty pieces), and their members are walked
+    by their lane.  The result equals the oracle's."""
+    g = _claim_graph()
+    rp, col = to_device(g, dev)
+    base = ctx.tuning()
+    ctx.set_tuning(**{**base, **tune})
+    try:
+        for s, dual in ((1, 0), (2, 0), (5, 0), (2, 1)):
+            print(f"case: claims {tune} s={s} dual={dual}", flush=True)
+            L = ctx.build(rp, col, g.n_vertices, s, dual)
+            ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, s, dual=dual,
+                                  threads=8)
+            assert_same(L, ref, f"claims {tune} s={s} dual={dual}")
+    finally:
+        ctx.set_tuning(**base)
+
+
 @pytest.mark.parametrize("tiny", [10, 4, 0])
 def test_tiny_items_one_per_lane(ctx, dev, tiny):
     """Builds with enough items (>= 32768) count their tiny items one per lane;
