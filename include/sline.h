@@ -367,7 +367,8 @@ sline_status sline_build_batch(sline_ctx *ctx, int32_t n_graphs, const sline_csr
  * Errors (outs untouched unless SLINE_OK):
  *   SLINE_EINVAL     bad arguments; a graph breaks the rules of sline_csr, or
  *                    its row_ptr[0] / row_ptr[m] changed since the plan was made;
- *                    a run's s below the planned s; flags other than
+ *                    a run's s below the planned s (checked before anything
+ *                    runs: the run changes nothing); flags other than
  *                    SLINE_NO_WEIGHTS.
  *   SLINE_ECAPACITY  the run needs more tasks or pairs than the plan holds
  *                    (changed contents); make a new plan.

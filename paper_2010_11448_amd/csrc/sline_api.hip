@@ -1424,6 +1424,7 @@ struct sline_batch_plan {
     uint32_t flags = 0;
     bool weights = true;
     std::vector<BatchGraph> gr;        // descriptors as last uploaded
+    bool gr_stale = false;             // an upload of gr may not have completed
     std::vector<int32_t> s_plan;       // each graph's planned s
     BatchBases B;
     int32_t s_min = 1;
@@ -1886,21 +1887,28 @@ sline_status plan_run_impl(sline_batch_plan *p, const int32_t *s, sline_edges *o
     }
     if (G == 0) return SLINE_OK;
     hipStream_t st = c->stream;
-    bool changed = false;
-    for (int32_t g = 0; g < G; ++g) {
-        const int32_t want = s ? s[g] : p->s_plan[g];
-        if (want < p->s_plan[g]) {
+    // every s is checked before any is taken: a refused run leaves the
+    // descriptors (host and device copies alike) as they were
+    for (int32_t g = 0; s && g < G; ++g) {
+        if (s[g] < p->s_plan[g]) {
             set_err(c, "batch plan: graph %s asks for an s below its planned s",
                     std::to_string(g).c_str());
             return SLINE_EINVAL;
         }
+    }
+    bool changed = p->gr_stale;
+    for (int32_t g = 0; g < G; ++g) {
+        const int32_t want = s ? s[g] : p->s_plan[g];
         changed = changed || want != p->gr[g].s;
         p->gr[g].s = want;
     }
-    if (changed)
+    if (changed) {
+        p->gr_stale = true;
         hip_check(c, hipMemcpyAsync(p->d_gr, p->gr.data(), sizeof(BatchGraph) * G,
                                     hipMemcpyHostToDevice, st),
                   "upload graphs");
+        p->gr_stale = false;
+    }
     hip_check(c, hipGraphLaunch(p->exec, st), "graph launch");
     int64_t *h = p->host;
     int64_t *w = h + G + 1;

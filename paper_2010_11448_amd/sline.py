@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -305,9 +306,12 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._alloc = torch_allocator(device) if torch_memory else None
         self.ctx = sline_create(device, self.stream.cuda_stream, self._alloc)
+        self._plans = weakref.WeakSet()  # open BatchPlans: destroyed before the context
 
     def close(self) -> None:
         if self.ctx:
+            for plan in list(self._plans):
+                plan.close()
             sline_destroy(self.ctx)
             self.ctx = None
 
@@ -595,6 +599,7 @@ class BatchPlan:
         if st != SLINE_OK:
             raise SlineError(st, sline_last_error(ctx.ctx))
         self._outs = (sline_edges * max(G, 1))()
+        ctx._plans.add(self)
 
     def info(self) -> tuple[int, int, int]:
         """(device bytes held, task capacity, pair capacity)."""
@@ -607,8 +612,12 @@ class BatchPlan:
 
     def run_raw(self, s=None) -> int:
         """One replay; returns the status (results in ``self._outs``)."""
+        if not self.plan:
+            raise RuntimeError("the batch plan is closed (or its context is)")
         sarr = None
         if s is not None:
+            if len(s) != self.G:
+                raise ValueError(f"{len(s)} values of s for {self.G} graphs")
             sarr = (ctypes.c_int32 * max(self.G, 1))(*[int(x) for x in s])
         return load().sline_batch_plan_run(self.plan, sarr, self._outs)
 
@@ -637,6 +646,7 @@ class BatchPlan:
         if self.plan:
             load().sline_batch_plan_destroy(self.plan)
             self.plan = None
+            self.ctx._plans.discard(self)
 
     def __del__(self):
         try:

@@ -104,6 +104,61 @@ def test_plan_runs_at_larger_s(ctx, dev):
         plan.close()
 
 
+def test_plan_refused_run_changes_no_s(ctx, dev):
+    """A run refused for one graph's s changes no graph's s: when an earlier
+    graph asked for a larger s in the refused run, the next run that asks
+    for that s counts it at that s (and a run at the planned s after that
+    counts every graph at its planned s)."""
+    from paper_2010_11448_amd import sline
+
+    graphs, ss, duals = _mixed_batch(12, 5)
+    dg = [to_device(h, dev) for h in graphs]
+
+    def count(g, s):
+        h = graphs[g]
+        ref, _ = oracle.wedge(h.row_ptr, h.col, h.n_edges, h.n_vertices, s, dual=duals[g],
+                              threads=8)
+        return len(ref.a)
+
+    # a graph whose L_s changes when its s goes up by two, then a later one
+    g0 = next(g for g in range(len(graphs) - 1) if count(g, ss[g]) != count(g, ss[g] + 2))
+    g1 = len(graphs) - 1
+    plan = _plan(ctx, dg, graphs, ss, duals)
+    try:
+        bad = list(ss)
+        bad[g0] = ss[g0] + 2
+        bad[g1] = ss[g1] - 1
+        print(f"case: plan refused run s={bad}", flush=True)
+        assert plan.run_raw(bad) == sline.SLINE_EINVAL
+        good = list(ss)
+        good[g0] = ss[g0] + 2
+        _check(plan.run(good), graphs, good, duals, "after a refused run")
+        _check(plan.run(), graphs, ss, duals, "planned s")
+    finally:
+        plan.close()
+
+
+def test_plan_closed_with_its_context(dev):
+    """Closing a context destroys its open plans first (a plan belongs to its
+    context): closing the plan afterwards does nothing and running it raises.
+    A run given the wrong number of s values is refused in the binding."""
+    from paper_2010_11448_amd import sline
+
+    graphs, ss, duals = _mixed_batch(4, 2)
+    dg = [to_device(h, dev) for h in graphs]
+    c = sline.Context(0)
+    plan = _plan(c, dg, graphs, ss, duals)
+    print("case: plan closed with its context", flush=True)
+    _check(plan.run(), graphs, ss, duals, "before the context closes")
+    with pytest.raises(ValueError):
+        plan.run_raw(ss[:-1])
+    c.close()
+    assert not plan.plan
+    plan.close()
+    with pytest.raises(RuntimeError):
+        plan.run()
+
+
 def _relabel_in_place(h, dual, rp, col, seed):
     """Rename the members of every item (vertices of a primal graph, edges of
     a dual one) by a random permutation and write the result into the same
