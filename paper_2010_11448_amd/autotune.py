@@ -28,7 +28,7 @@ SPACE: dict[str, list[int]] = {
     "task_slots": [4480, 8960, 13440, 17920],
     "tiny_max_wedges": [0, 4, 10],
     "small_max_wedges": [0, 128, 256, 512, 1024],
-    "light_len": [2, 4, 8, 16],
+    "light_len": [2, 4, 8, 12, 16],
     "small_grid_per_cu": [4, 8, 16, 32],
     "task_grid_per_cu": [2, 3, 4],
     "dense_min_wedges": [0, 1024, 4096, 16384],
@@ -115,8 +115,11 @@ def batch_signature(graphs, s, dual=None) -> str:
 class cached_tuning:
     """Inside the block, ``ctx`` runs with the tuning stored for ``sig`` in the
     cache file at ``path`` (merged over its own); its own tuning comes back on
-    exit.  No file, no entry or ``path`` None: nothing changes.  The value of
-    the block is the applied entry, or None."""
+    exit.  No file, no entry or ``path`` None: nothing changes.  The cache is a
+    speed hint, never a reason for a call to fail: parameters the context does
+    not have are left out, and an entry the context refuses (a value outside
+    its ranges) is not applied.  The value of the block is the applied entry,
+    or None."""
 
     def __init__(self, ctx, path: str | None, sig: str):
         self.ctx, self.path, self.sig = ctx, path, sig
@@ -124,9 +127,16 @@ class cached_tuning:
 
     def __enter__(self):
         entry = load_cached(self.path, self.sig) if self.path else None
-        if entry:
-            self.prev = self.ctx.tuning()
-            self.ctx.set_tuning(**{**self.prev, **entry})
+        if not entry:
+            return None
+        prev = self.ctx.tuning()
+        entry = {k: v for k, v in entry.items() if k in prev}
+        try:
+            self.ctx.set_tuning(**{**prev, **entry})
+        except Exception:
+            self.ctx.set_tuning(**prev)
+            return None
+        self.prev = prev
         return entry
 
     def __exit__(self, *exc):

@@ -83,3 +83,29 @@ def test_cached_tuning_applies_and_restores(tmp_path):
         assert entry is None and ctx.tuning() == before
     with autotune.cached_tuning(ctx, None, sig) as entry:
         assert entry is None and ctx.tuning() == before
+
+
+def test_cached_tuning_skips_what_the_context_refuses(tmp_path):
+    """An entry's parameters the context does not have are left out, and an
+    entry whose values the context refuses is not applied: the call goes on
+    with the context's own tuning."""
+
+    class Strict(FakeCtx):
+        def set_tuning(self, **kw):
+            if kw["task_wedges"] < 64:
+                raise ValueError("tuning value out of range")
+            super().set_tuning(**kw)
+
+    ctx = Strict()
+    path = str(tmp_path / "tune.json")
+    sig = autotune.signature([1000], [1], [0])
+    before = ctx.tuning()
+    autotune.save_cached(path, sig, {"task_wedges": 7000, "not_a_parameter": 32}, 0.5)
+    with autotune.cached_tuning(ctx, path, sig) as entry:
+        assert entry == {"task_wedges": 7000}
+        assert ctx.tuning() == {**before, "task_wedges": 7000}
+    assert ctx.tuning() == before
+    autotune.save_cached(path, sig, {"task_wedges": 1}, 0.5)
+    with autotune.cached_tuning(ctx, path, sig) as entry:
+        assert entry is None and ctx.tuning() == before
+    assert ctx.tuning() == before
