@@ -109,3 +109,64 @@ def test_every_entry_point_rejects_a_null_handle_without_gpu():
     covered = set(calls) | {"sline_server_last_error", "sline_server_destroy", "sline_destroy",
                             "sline_last_error", "sline_status_str", "sline_batch_plan_destroy"}
     assert set(declared_functions()) <= covered
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets: a C program built against include/sline.h prints them."""
+    import shutil
+    import subprocess
+
+    import pytest
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [sline.sline_csr, sline.sline_edges, sline.sline_stats, sline.sline_tuning,
+               sline.sline_graph, sline.sline_query_info, sline.sline_allocator]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sline.h"',
+             "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'    printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'    printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    c_side = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        name, field, value = line.split()
+        c_side[(name, field)] = int(value)
+    for st in structs:
+        name = st.__name__
+        assert c_side[(name, "sizeof")] == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert c_side[(name, field)] == getattr(st, field).offset, f"{name}.{field}"
+    # the same fields, in the same order (a field missing at the end can hide
+    # in the struct's padding)
+    fields = header_struct_fields()
+    for st in structs:
+        assert [f for f, _ in st._fields_] == fields[st.__name__], st.__name__
+
+
+def header_struct_fields() -> dict[str, list[str]]:
+    """Field names, in order, of every `typedef struct { ... } name;` in the
+    public header."""
+    text = open(os.path.join(ROOT, "include", "sline.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            fp = re.search(r"\(\s*\*\s*(\w+)\s*\)", decl)  # function pointer
+            names.append(fp.group(1) if fp else re.findall(r"\w+", decl)[-1])
+        out[name] = names
+    return out
