@@ -62,7 +62,10 @@ TUNE_CACHE = os.path.join(HERE, "paper_2010_11448_amd", "tuning_cache.json")
 
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(ROOT, "paper_2010_11448_amd", "csrc", "sline_count.hip")
+# the counting kernels and their default launch parameters (Tuning): counter
+# figures taken on other sources or defaults do not apply
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2010_11448_amd", "csrc", f)
+               for f in ("sline_count.hip", "sline_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_count_tasks_powerlaw_1Mx2M_traffic.md")
 
 
@@ -203,8 +206,11 @@ def gen_mod():
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in KERNEL_SRCS:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def committed_traffic(form):

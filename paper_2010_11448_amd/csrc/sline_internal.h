@@ -28,7 +28,7 @@ struct Tuning {
     int32_t small_max_wedges = 512;  // items with W_a up to this go to the one-wave kernel
     int32_t task_wedges = 5000;      // wedges per workgroup task (j sub-range of an item)
     int32_t group_parts = 8;         // consecutive tasks of one item run by one workgroup
-    int32_t light_len = 8;           // member runs up to this are walked by one lane
+    int32_t light_len = 12;          // member runs up to this are walked by one lane
     int32_t small_grid_per_cu = 16;  // one-wave workgroups per CU for the small kernel
     int32_t task_grid_per_cu = 4;    // resident workgroups per CU for the task kernel
     int64_t stage_max_bytes = 96ll << 30;  // cap of the staging pool (one counting pass)
