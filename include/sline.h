@@ -110,7 +110,9 @@ typedef struct {
  *                 If the result needs more, the call returns SLINE_ECAPACITY
  *                 with n_pairs = the entries needed, writes nothing else, and
  *                 keeps its counting work: an immediate repeat of the same
- *                 call with larger buffers only writes the result. */
+ *                 call with larger buffers only writes the result (the input
+ *                 is not read again: change its contents in between and the
+ *                 repeat still gives the first contents' result). */
 typedef struct {
     int64_t n_pairs;
     int64_t capacity;
@@ -330,7 +332,8 @@ sline_status sline_build_spgemm(sline_ctx *ctx, sline_csr H, int32_t s, int32_t 
  *              supplies caller buffers.  If any graph's buffers are too small
  *              the call returns SLINE_ECAPACITY, sets n_pairs of every graph
  *              and writes no pairs; an immediate retry with the same
- *              arguments (larger buffers) reuses the computed result.
+ *              arguments (larger buffers) reuses the computed result (the
+ *              graphs are not read again).
  * Errors: SLINE_EINVAL if any graph is malformed (as in sline_build) or any
  * s[g] < 1 / dual[g] not in {0, 1}; the combined item and member counts and
  * incidences must each stay below 2^31.  Other codes as above. */
