@@ -2111,7 +2111,6 @@ sline_status spgemm_impl(sline_ctx *c, const sline_csr &H, int32_t s, int32_t du
 namespace {
 
 constexpr uint32_t kRelabelFlags = SLINE_RELABEL_DESC | SLINE_RELABEL_ASC;
-constexpr uint32_t kVariantFlags = SLINE_NO_PRUNE | SLINE_NO_VISITED | SLINE_NO_SHORTCUT;
 
 // One device block for the temporaries of a call, carved by an Arena and
 // released (after the stream is idle) when the call leaves.

@@ -79,10 +79,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint32_t lds_load(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 // first index p in [lo, hi) with arr[p] >= key (arr ascending), hi if none
 __device__ __forceinline__ int32_t lower_bound(const int32_t *arr, int32_t lo, int32_t hi,
                                                int32_t key) {

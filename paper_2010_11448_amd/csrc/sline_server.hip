@@ -379,7 +379,7 @@ void keep_result(sline_server *S, int32_t graph, int32_t dual, int32_t s, const 
     evict_kept(S, S->reuse_cap);
 }
 
-int64_t estimate(const sline_server *S, const Graph &g, int32_t s, int32_t dual) {
+int64_t estimate(const Graph &g, int32_t s, int32_t dual) {
     const double N = dual ? g.H.n_vertices : g.H.n_edges;
     const double pairs = std::min(g.w1[dual] / std::max(s, 1), N * (N - 1.0) / 2.0);
     return (int64_t)(80.0 * (double)g.nnz + 20.0 * pairs) + (1 << 20);
@@ -462,7 +462,7 @@ void worker_loop(sline_server *S, int wi) {
                     const int64_t qe =
                         can_reuse ? kt->second.bytes + ((int64_t)1 << 20)
                         : s_build == q.s ? q.est
-                                         : estimate(S, S->graphs[q.graph], s_build, q.dual);
+                                         : estimate(S->graphs[q.graph], s_build, q.dual);
                     // results the client has not released count against the
                     // budget too (so a slow client holds back admission); kept
                     // results live beside the budget, within their own cap,
@@ -789,7 +789,7 @@ sline_status sline_server_submit(sline_server *S, int32_t graph_id, int32_t s, i
         q.graph = graph_id;
         q.s = s;
         q.dual = dual;
-        q.est = estimate(S, S->graphs[graph_id], s, dual);
+        q.est = estimate(S->graphs[graph_id], s, dual);
         q.s_build = s;
         q.info.t_submit_ns = now_ns();
         q.info.status = SLINE_EBUSY;
