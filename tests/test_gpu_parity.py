@@ -101,10 +101,17 @@ def test_edge_cases(ctx, dev):
     g = gen.from_sets([[0, 1, 2]], 3)
     _check(ctx, dev, g, 1, 0, "single")
     _check(ctx, dev, g, 1, 1, "single dual")
-    # s above every size
+    # s above every size, up to the largest int32
     g = gen.uniform_2000(11)
     rpd, cold = to_device(g, dev)
     assert len(ctx.build(rpd, cold, g.n_vertices, 21, 0)) == 0
+    for dual in (0, 1):
+        assert len(ctx.build(rpd, cold, g.n_vertices, 2 ** 31 - 1, dual)) == 0
+    # in a batch beside a graph with pairs
+    both = ctx.build_batch([(rpd, cold, g.n_vertices)] * 2, [2 ** 31 - 1, 2], [0, 0])
+    assert len(both[0]) == 0
+    ref, _ = oracle.wedge(g.row_ptr, g.col, g.n_edges, g.n_vertices, 2, dual=0, threads=8)
+    assert_same(both[1], ref, "batch beside s = 2^31 - 1")
     # identical rows
     g = gen.from_sets([[1, 3, 5]] * 5 + [[0], []], 6)
     for s in (1, 3, 4):
