@@ -160,8 +160,9 @@ typedef struct {
  *   task_wedges        wedges per workgroup task, the unit an item's candidate
  *                      range is cut into (64..1048576)
  *   group_parts        consecutive tasks of one item run by one workgroup (1..1024)
- *   light_len          member runs expected shorter than this are walked by a
- *                      single lane (0..64)
+ *   light_len          member runs expected to have at most this many entries
+ *                      in a task's range are walked by a single lane (0..64;
+ *                      default 12)
  *   small_grid_per_cu  resident one-wave workgroups per CU (1..64)
  *   task_grid_per_cu   resident task workgroups per CU (1..16)
  *   stage_max_bytes    cap of the staging pool that lets one counting pass
